@@ -1,0 +1,199 @@
+"""ctypes front end of the FP64 C oracle (``sobrc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline of the benchmark.  The product package never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sobrc_oracle.c")
+LIB = os.path.join(HERE, "libsobrc_oracle.so")
+
+PC, PS = 0, 1
+MODE_SOBOLEV, MODE_L2 = 0, 1
+NEIGH_BRUTE, NEIGH_CELLS = 0, 1
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("model", C.c_int32), ("ps_radius", C.c_int32),
+        ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
+        ("max_labels", C.c_int32), ("threads", C.c_int32),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                               "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        P = C.POINTER
+        L.ora_kernel.restype = C.c_double
+        L.ora_kernel.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.ora_particles.restype = C.c_int64
+        L.ora_particles.argtypes = [P(Params), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_region_stats.restype = None
+        L.ora_region_stats.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_l2diff.restype = None
+        L.ora_l2diff.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_sobolev.restype = None
+        L.ora_sobolev.argtypes = [P(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p]
+        L.ora_step.restype = C.c_int64
+        L.ora_step.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p]
+        L.ora_run.restype = C.c_int32
+        L.ora_run.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                              C.c_double, C.c_void_p, C.c_void_p]
+        L.ora_energy_pc.restype = C.c_double
+        L.ora_energy_pc.argtypes = [P(Params), C.c_void_p, C.c_void_p]
+        L.ora_conv_closed_curve.restype = None
+        L.ora_conv_closed_curve.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double,
+                                            C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def make_params(shape, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0, max_labels=2,
+                threads=1) -> Params:
+    if len(shape) == 2:
+        ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
+    else:
+        ndim, (nz, ny, nx) = 3, shape
+    return Params(ndim, nx, ny, nz, model, ps_radius, float(E), float(eps), float(lam),
+                  max_labels, threads)
+
+
+def params_of(w, threads=1) -> Params:
+    """Parameters of a workloads.Workload."""
+    return make_params(w.image.shape, w.E, w.lam, w.model, w.ps_radius, w.eps,
+                       w.max_labels, threads)
+
+
+def _img(I):
+    return np.ascontiguousarray(I, dtype=np.float64)
+
+
+def _lab(L):
+    return np.ascontiguousarray(L, dtype=np.int32)
+
+
+def kernel(r, E, eps=1.0 / 24.0) -> float:
+    return lib().ora_kernel(float(r), float(E), float(eps))
+
+
+def particles(P: Params, L):
+    L = _lab(L)
+    n = lib().ora_particles(C.byref(P), _ptr(L), 0, None, None, None)
+    lin = np.zeros(n, np.int64)
+    a = np.zeros(n, np.int32)
+    b = np.zeros(n, np.int32)
+    lib().ora_particles(C.byref(P), _ptr(L), n, _ptr(lin), _ptr(a), _ptr(b))
+    return lin, a, b
+
+
+def region_stats(P: Params, I, L):
+    M = P.max_labels
+    n = np.zeros(M, np.int64)
+    s1 = np.zeros(M)
+    s2 = np.zeros(M)
+    I, L = _img(I), _lab(L)
+    lib().ora_region_stats(C.byref(P), _ptr(I), _ptr(L), _ptr(n), _ptr(s1), _ptr(s2))
+    return n, s1, s2
+
+
+def l2diff(P: Params, I, L, lin, a, b):
+    I, L = _img(I), _lab(L)
+    lin = np.ascontiguousarray(lin, np.int64)
+    a = np.ascontiguousarray(a, np.int32)
+    b = np.ascontiguousarray(b, np.int32)
+    out = np.zeros(len(lin))
+    lib().ora_l2diff(C.byref(P), _ptr(I), _ptr(L), len(lin), _ptr(lin), _ptr(a), _ptr(b), _ptr(out))
+    return out
+
+
+def sobolev(P: Params, lin, a, b, dE, neigh=NEIGH_CELLS, sel=None):
+    lin = np.ascontiguousarray(lin, np.int64)
+    a = np.ascontiguousarray(a, np.int32)
+    b = np.ascontiguousarray(b, np.int32)
+    dE = np.ascontiguousarray(dE, np.float64)
+    if sel is not None:
+        sel = np.ascontiguousarray(sel, np.int64)
+        out = np.zeros(len(sel))
+        lib().ora_sobolev(C.byref(P), len(lin), _ptr(lin), _ptr(a), _ptr(b), _ptr(dE),
+                          _ptr(out), neigh, len(sel), _ptr(sel))
+    else:
+        out = np.zeros(len(lin))
+        lib().ora_sobolev(C.byref(P), len(lin), _ptr(lin), _ptr(a), _ptr(b), _ptr(dE),
+                          _ptr(out), neigh, 0, None)
+    return out
+
+
+def step(P: Params, I, L, mode=MODE_SOBOLEV, want_arrays=True):
+    """One iteration.  Returns (L_next, dict) with the particle list and both
+    gradients of the state the step started from."""
+    I = _img(I)
+    L = _lab(L).copy()
+    nf = C.c_int64(0)
+    if not want_arrays:
+        n = lib().ora_step(C.byref(P), _ptr(I), _ptr(L), mode, 0, None, None, None, None, None,
+                           C.byref(nf))
+        return L, {"n": n, "flips": nf.value}
+    n = lib().ora_particles(C.byref(P), _ptr(L), 0, None, None, None)
+    lin = np.zeros(n, np.int64)
+    a = np.zeros(n, np.int32)
+    b = np.zeros(n, np.int32)
+    g2 = np.zeros(n)
+    g1 = np.zeros(n)
+    r = lib().ora_step(C.byref(P), _ptr(I), _ptr(L), mode, n, _ptr(lin), _ptr(a), _ptr(b),
+                       _ptr(g2), _ptr(g1), C.byref(nf))
+    assert r == n
+    return L, {"n": n, "flips": nf.value, "lin": lin, "a": a, "b": b, "dE_l2": g2, "dE_h1": g1}
+
+
+def run(P: Params, I, L, mode=MODE_SOBOLEV, max_iters=100, tol=0.0):
+    I = _img(I)
+    L = _lab(L).copy()
+    hn = np.zeros(max_iters, np.int64)
+    hf = np.zeros(max_iters, np.int64)
+    t = lib().ora_run(C.byref(P), _ptr(I), _ptr(L), mode, max_iters, float(tol), _ptr(hn), _ptr(hf))
+    return L, t, hn[:t], hf[:t]
+
+
+def energy_pc(P: Params, I, L) -> float:
+    I, L = _img(I), _lab(L)
+    return lib().ora_energy_pc(C.byref(P), _ptr(I), _ptr(L))
+
+
+def conv_closed_curve(g, Lc, E, eps=1.0 / 24.0):
+    g = np.ascontiguousarray(g, np.float64)
+    out = np.zeros_like(g)
+    lib().ora_conv_closed_curve(len(g), float(Lc), float(E), float(eps), _ptr(g), _ptr(out))
+    return out

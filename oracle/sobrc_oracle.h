@@ -1,0 +1,90 @@
+/* sobrc_oracle.h -- FP64 CPU oracle for particle-based Region Competition with
+ * particle-approximated Sobolev gradients (Sbalzarini, Schneider, Cardinale,
+ * arXiv:1403.0240).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the HIP implementation; the two agree only
+ * because both follow the paper.
+ *
+ * Layout: images and label fields are [nz][ny][nx], x fastest; 2D means nz = 1.
+ * Linear index i = x + nx*(y + ny*z).  Labels: 0 = background, 1..M-1 foreground.
+ */
+#ifndef SOBRC_ORACLE_H
+#define SOBRC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_PC = 0, ORA_PS = 1 };
+enum { ORA_MODE_SOBOLEV = 0, ORA_MODE_L2 = 1 };
+enum { ORA_NEIGH_BRUTE = 0, ORA_NEIGH_CELLS = 1 };
+
+typedef struct {
+    int32_t ndim, nx, ny, nz;  /* nz = 1 when ndim = 2 */
+    int32_t model;             /* ORA_PC or ORA_PS */
+    int32_t ps_radius;         /* PS local-mean ball: |y-x|^2 <= R^2 */
+    double E, eps, lambda;     /* Sobolev length scale, smoothness, prior weight */
+    int32_t max_labels;
+    int32_t threads;           /* OpenMP threads for per-particle loops (<=1: serial) */
+} ora_params;
+
+/* Sobolev kernel of Eq. (5); zero outside its support |r| <= E/2. */
+double ora_kernel(double r, double E, double eps);
+
+/* Contour particle set (Fig. 1 and the particle-representation section): one
+ * particle (i, a = L(i), b) per pixel i and per distinct label b != a found in
+ * its full neighbourhood (8 in 2D, 26 in 3D).  Canonical order: i, then b.
+ * Writes at most cap entries; returns the total count. */
+int64_t ora_particles(const ora_params* P, const int32_t* L, int64_t cap,
+                      int64_t* lin, int32_t* a, int32_t* b);
+
+/* Region statistics over the label field: n_l, sum I, sum I^2. */
+void ora_region_stats(const ora_params* P, const double* I, const int32_t* L,
+                      int64_t* n, double* s1, double* s2);
+
+/* L2-type gradient: per-particle energy difference of the single move
+ * a -> b (Eqs. (10)-(11)), piecewise-constant or piecewise-smooth model plus
+ * lambda times the change in contour length. */
+void ora_l2diff(const ora_params* P, const double* I, const int32_t* L,
+                int64_t np, const int64_t* lin, const int32_t* a, const int32_t* b,
+                double* dE);
+
+/* Discrete Sobolev update, Eq. (6).  If sel != NULL only the nsel particles
+ * listed there are evaluated and out[k] belongs to particle sel[k]; otherwise
+ * out has np entries.  neigh selects brute force or cell lists. */
+void ora_sobolev(const ora_params* P, int64_t np, const int64_t* lin,
+                 const int32_t* a, const int32_t* b, const double* dE_in,
+                 double* out, int32_t neigh, int64_t nsel, const int64_t* sel);
+
+/* One Region Competition iteration on L (in place): particles, stats, L2
+ * gradient, Sobolev smoothing (mode), simultaneous acceptance.  Optional
+ * outputs (may be NULL, each needs cap entries): particle list and both
+ * gradients.  Returns the particle count N_t (or -1 if N_t > cap while an
+ * output array was requested); *nflips receives the number of changed pixels. */
+int64_t ora_step(const ora_params* P, const double* I, int32_t* L, int32_t mode,
+                 int64_t cap, int64_t* lin, int32_t* a, int32_t* b,
+                 double* dE_l2, double* dE_h1, int64_t* nflips);
+
+/* Repeat ora_step until max_iters or nflips < tol * N_t.  Per-iteration N_t
+ * and flips go to hist_n / hist_f (max_iters entries each, may be NULL).
+ * Returns iterations done. */
+int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
+                int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f);
+
+/* Total piecewise-constant energy: sum_x (I(x) - mu_{L(x)})^2 with region means
+ * mu_l, plus lambda times the number of face-adjacent pixel pairs with
+ * different labels (discrete contour length). */
+double ora_energy_pc(const ora_params* P, const double* I, const int32_t* L);
+
+/* Continuous form of Eq. (4) on a closed curve of arc length Lc sampled at n
+ * equispaced points: out_i = sum_j K(geodesic(s_i, s_j)) g_j (Lc/n). */
+void ora_conv_closed_curve(int64_t n, double Lc, double E, double eps,
+                           const double* g, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
