@@ -1,0 +1,186 @@
+/* sobrc.h -- C ABI of the MI355X (gfx950) implementation of the per-iteration
+ * hot path of particle-based Region Competition with particle-approximated
+ * Sobolev gradients (Sbalzarini, Schneider, Cardinale, arXiv:1403.0240).
+ *
+ * One iteration on the contour particles:
+ *   compute_l2_diff : L2-type gradient of every particle, i.e. the energy change
+ *                     of its single move (Eqs. (10)-(11), region models from the
+ *                     Methods section);
+ *   sobolev_smooth  : the discrete Sobolev update of Eq. (6), kernel of Eq. (5),
+ *                     neighbours found with cell lists (text after Eq. (6));
+ *   step / run      : acceptance of moves, label update and contour-particle
+ *                     bookkeeping, repeated until a flip-rate tolerance.
+ *
+ * Conventions shared by every entry point
+ *  - Every function is extern "C", returns an int32 status (SOBRC_OK = 0 or a
+ *    negative SOBRC_E* code) and never throws.  last_error() returns a
+ *    thread-local message describing the last failure of this thread.
+ *  - "d_" pointers are device (HIP) pointers, "h_" pointers host pointers.
+ *    All device memory is owned by the caller; the library never allocates
+ *    device memory.  A context lives in a caller-provided device workspace of
+ *    workspace_size() bytes and borrows the image until ctx_destroy.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream unless stated otherwise.  One
+ *    context must not be used from two streams at once.
+ *  - Grids: images and label fields are [nz][ny][nx], x fastest, nz = 1 for 2D;
+ *    pixel centres sit at integer coordinates; linear index i = x + nx*(y + ny*z).
+ *    Labels are in [0, max_labels); 0 is the single background region (an open
+ *    set), 1.. are foreground regions (closed sets), as in the Methods.
+ *  - Contour particles: one particle (i, a = L(i), b) for every pixel i and
+ *    every distinct label b != a among its in-bounds full neighbours (8 in 2D,
+ *    26 in 3D), i.e. particles on both sides of the contour (Fig. 1).  The
+ *    library's particle order is tile-major (tiles of 16x16 pixels in 2D,
+ *    8x8x8 voxels in 3D, tiles in x-fastest order), then the pixel's position
+ *    inside the tile (x fastest), then b ascending.  All per-particle arrays of
+ *    a context use that order.
+ */
+#ifndef SOBRC_H
+#define SOBRC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SOBRC_OK = 0,
+    SOBRC_EINVAL = -1,     /* bad parameter, null pointer, label out of range */
+    SOBRC_ECAPACITY = -2,  /* particle count would exceed max_particles */
+    SOBRC_EDEVICE = -3,    /* HIP runtime error (message kept in last_error) */
+    SOBRC_ESTATE = -4      /* call order (e.g. step before init_labels) */
+};
+enum { SOBRC_F32 = 0, SOBRC_U16 = 1 };            /* image element type */
+enum { SOBRC_PC = 0, SOBRC_PS = 1 };              /* piecewise constant / smooth */
+enum { SOBRC_MODE_SOBOLEV = 0, SOBRC_MODE_L2 = 1 };
+
+typedef struct {
+    int32_t ndim;          /* 2 or 3 */
+    int32_t nx, ny, nz;    /* 3D: each in [1, 1024]; 2D: nx, ny in [1, 32768], nz = 1 */
+    int32_t image_dtype;   /* SOBRC_F32 or SOBRC_U16 */
+    int32_t model;         /* SOBRC_PC or SOBRC_PS */
+    int32_t ps_radius;     /* PS local-mean ball |y-x|^2 <= R^2, R in [2, 32]; ignored for PC */
+    double E;              /* Sobolev length scale, 0 < E <= 64; interaction radius E/2 */
+    double eps;            /* smoothness hyper-parameter of Eq. (1), > 0 (paper: 1/24) */
+    double lambda;         /* prior weight of Eq. (10), >= 0 */
+    int32_t max_labels;    /* labels lie in [0, max_labels), 2 <= max_labels <= 65535 */
+    int64_t max_particles; /* particle capacity, 1 <= max_particles < 2^31 */
+} sobrc_params;
+
+typedef struct sobrc_ctx sobrc_ctx;
+
+/* Bytes of device workspace a context with these parameters needs.
+ * Host only, no device call.  EINVAL on bad parameters. */
+int32_t workspace_size(const sobrc_params* params, size_t* bytes);
+
+/* Create a context inside a caller-owned device workspace (d_workspace,
+ * 256-byte aligned, at least workspace_size bytes).  Host only: no device call
+ * is made until init_labels.  *out receives a library-owned host handle. */
+int32_t ctx_create(const sobrc_params* params, void* d_workspace, size_t bytes,
+                   sobrc_ctx** out);
+
+/* Release the host handle (the workspace stays the caller's).  Synchronises
+ * with nothing; the caller must not destroy a context with work in flight. */
+int32_t ctx_destroy(sobrc_ctx* ctx);
+
+/* Start a segmentation job: copy the initial label field (int32, nvox entries)
+ * into the workspace, compute region statistics (photometric estimate: region
+ * mean intensities, Methods) and build the contour particle set.  The context
+ * borrows d_image (nvox elements of image_dtype) until ctx_destroy.
+ * Synchronises `stream` once.  EINVAL if a label is outside [0, max_labels),
+ * ECAPACITY if the particle set exceeds max_particles (the context then stays
+ * uninitialised).  Resuming from a checkpoint is init_labels with saved labels. */
+int32_t init_labels(sobrc_ctx* ctx, const void* d_image, const int32_t* d_labels,
+                    void* stream);
+
+/* L2-type gradient (energy difference of each particle's single move a -> b,
+ * Eq. (11) with E_ext + lambda E_int of Eq. (10)): piecewise-constant data
+ * term with re-estimated region means, or piecewise-smooth local means over
+ * the PS ball; plus lambda times the change of the number of face-adjacent
+ * pixel pairs with different labels (contour-length prior).  Writes fp32
+ * values for the current particles, in context order, to d_dE_l2 (room for
+ * max_particles entries).  Asynchronous. */
+int32_t compute_l2_diff(sobrc_ctx* ctx, float* d_dE_l2, void* stream);
+
+/* Discrete Sobolev update of Eq. (6) on the current particles: for particle p,
+ *   out_p = (1/|Q_p|) sum_{q in Q_p} K(d_pq) in_q - (1/|Q'_p|) sum_{q in Q'_p} K(d_pq) in_q
+ * with Q_p the particles of the same label pair (a, b) (p included), Q'_p those
+ * of the swapped pair (b, a), both within Euclidean distance d_pq < E/2, K the
+ * kernel of Eq. (5), and the second term 0 when Q'_p is empty.  Reads
+ * d_dE_l2, writes d_dE_h1 (distinct buffers, context order, fp32 with fp32
+ * accumulation).  Asynchronous. */
+int32_t sobolev_smooth(sobrc_ctx* ctx, const float* d_dE_l2, float* d_dE_h1, void* stream);
+
+/* One iteration: L2 gradient, Sobolev update (mode SOBOLEV) or none (mode L2),
+ * acceptance -- every particle with gradient < 0 is a candidate, per pixel the
+ * smallest gradient wins (ties: smaller b), all chosen moves applied together
+ * -- then region statistics and the particle set are brought up to date.
+ * If d_nflips != NULL the number of changed pixels is written there (device
+ * int32).  Asynchronous, no host synchronisation.  If the new particle set
+ * would exceed max_particles the step is rolled back on the device and the
+ * context reports ECAPACITY from its next synchronising call (ctx_sync, run,
+ * get_particles); further steps do nothing until a new init_labels. */
+int32_t step(sobrc_ctx* ctx, int32_t mode, int32_t* d_nflips, void* stream);
+
+/* Up to max_iters iterations; stops after the first iteration t whose flip
+ * count is below flip_tol * N_t (N_t = particles at the start of t; flip_tol
+ * = 0 runs all iterations).  The stop is decided on the device, so the result
+ * does not depend on how often the host looks.  Synchronises at the end;
+ * *h_iters_done (may be NULL) receives the iterations executed. */
+int32_t run(sobrc_ctx* ctx, int32_t max_iters, double flip_tol, int32_t mode,
+            int32_t* h_iters_done, void* stream);
+
+/* Synchronise `stream` and report the context's device-side status
+ * (SOBRC_OK, SOBRC_ECAPACITY after an overflowing step). */
+int32_t ctx_sync(sobrc_ctx* ctx, void* stream);
+
+/* Current particle count (synchronises) and, for non-NULL arrays (each with
+ * room for *h_n entries), the particles in context order: linear pixel index,
+ * own label a and target label b (int32). */
+int32_t get_particles(sobrc_ctx* ctx, int64_t* h_n, int32_t* d_lin, int32_t* d_a,
+                      int32_t* d_b, void* stream);
+
+/* Copy the current label field to d_labels (int32, nvox).  Asynchronous. */
+int32_t get_labels(sobrc_ctx* ctx, int32_t* d_labels, void* stream);
+
+/* Region statistics per label (synchronises): pixel count and intensity sum
+ * (h_sum may be NULL).  Sums are kept exactly: integers for uint16 images,
+ * 2^-s fixed point for fp32 images (s chosen at init_labels from max |I|). */
+int32_t get_region_stats(sobrc_ctx* ctx, int64_t* h_count, double* h_sum, void* stream);
+
+/* Per-iteration telemetry of the last iterations (synchronises): for up to
+ * `cap` most recent iterations, particle count N_t and flips_t, oldest first.
+ * *h_len receives the number written. */
+int32_t get_history(sobrc_ctx* ctx, int32_t cap, int32_t* h_n, int32_t* h_flips,
+                    int32_t* h_len, void* stream);
+
+/* Stateless Eq. (6) on caller-given particles (any order, n >= 0): positions
+ * as linear indices d_lin, labels d_a != d_b in [0, max_labels), values d_in;
+ * writes d_out in the input order.  Needs a device workspace of
+ * sobolev_particles_workspace_size bytes.  Synchronises once to validate the
+ * particles (EINVAL on bad input).  fp32 sums are summed in an order that
+ * depends on the binning, so repeated calls may differ in the last bits. */
+int32_t sobolev_particles_workspace_size(const sobrc_params* params, int64_t n,
+                                         size_t* bytes);
+int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n,
+                                 const int32_t* d_lin, const int32_t* d_a,
+                                 const int32_t* d_b, const float* d_in, float* d_out,
+                                 void* d_workspace, size_t ws_bytes, void* stream);
+
+/* Kernel timing with HIP events on the launch stream.  profile_enable(ctx, 1)
+ * records an event pair around every kernel the context launches;
+ * profile_read synchronises and returns, per kernel kind k (see
+ * SOBRC_K_* below), the summed milliseconds and launch count since the last
+ * reset.  Kinds: */
+enum { SOBRC_K_L2DIFF = 0, SOBRC_K_SOBOLEV = 1, SOBRC_K_FLIP = 2, SOBRC_K_COUNT = 3,
+       SOBRC_K_SCAN = 4, SOBRC_K_WRITE = 5, SOBRC_K_NKINDS = 6 };
+int32_t profile_enable(sobrc_ctx* ctx, int32_t on);
+int32_t profile_read(sobrc_ctx* ctx, double* h_ms, int64_t* h_launches, int32_t reset);
+
+const char* last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOBRC_H */

@@ -1,0 +1,706 @@
+// sobrc_abi.hip -- extern "C" entry points declared in include/sobrc.h.
+//
+// Host-side work only: parameter validation, workspace layout, the kernel
+// table W[d^2] of Eq. (5) in FP64, launch sequencing and error reporting.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "sobrc.h"
+#include "sobrc_dev.h"
+
+using namespace sobrc;
+
+namespace {
+
+thread_local char g_err[512];
+
+int32_t fail(int32_t code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int32_t dev_fail(hipError_t e, const char* where)
+{
+    return fail(SOBRC_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define SOBRC_HIP(call, where)                 \
+    do {                                       \
+        hipError_t e_ = (call);                \
+        if (e_ != hipSuccess)                  \
+            return dev_fail(e_, where);        \
+    } while (0)
+
+int log2_exact(int v)
+{
+    int s = 0;
+    while ((1 << s) < v)
+        ++s;
+    return s;
+}
+
+int32_t validate(const sobrc_params* p)
+{
+    if (!p)
+        return fail(SOBRC_EINVAL, "params is NULL");
+    if (p->ndim != 2 && p->ndim != 3)
+        return fail(SOBRC_EINVAL, "ndim must be 2 or 3 (got %d)", p->ndim);
+    int lim = p->ndim == 3 ? 1024 : 32768;
+    if (p->nx < 1 || p->ny < 1 || p->nx > lim || p->ny > lim)
+        return fail(SOBRC_EINVAL, "nx, ny must lie in [1, %d] (got %d, %d)", lim, p->nx, p->ny);
+    if (p->ndim == 2 && p->nz != 1)
+        return fail(SOBRC_EINVAL, "2D images need nz = 1 (got %d)", p->nz);
+    if (p->ndim == 3 && (p->nz < 1 || p->nz > 1024))
+        return fail(SOBRC_EINVAL, "nz must lie in [1, 1024] (got %d)", p->nz);
+    if (p->image_dtype != SOBRC_F32 && p->image_dtype != SOBRC_U16)
+        return fail(SOBRC_EINVAL, "image_dtype must be SOBRC_F32 or SOBRC_U16");
+    if (p->model != SOBRC_PC && p->model != SOBRC_PS)
+        return fail(SOBRC_EINVAL, "model must be SOBRC_PC or SOBRC_PS");
+    if (p->model == SOBRC_PS && (p->ps_radius < 2 || p->ps_radius > 32))
+        return fail(SOBRC_EINVAL, "ps_radius must lie in [2, 32] (got %d)", p->ps_radius);
+    if (!(p->E > 0.0 && p->E <= 64.0))
+        return fail(SOBRC_EINVAL, "E must lie in (0, 64] (got %g)", p->E);
+    if (!(p->eps > 0.0 && isfinite(p->eps)))
+        return fail(SOBRC_EINVAL, "eps must be positive (got %g)", p->eps);
+    if (!(p->lambda >= 0.0 && isfinite(p->lambda)))
+        return fail(SOBRC_EINVAL, "lambda must be >= 0 (got %g)", p->lambda);
+    if (p->max_labels < 2 || p->max_labels > 65535)
+        return fail(SOBRC_EINVAL, "max_labels must lie in [2, 65535] (got %d)", p->max_labels);
+    if (p->max_particles < 1 || p->max_particles > 0x7fffffffLL)
+        return fail(SOBRC_EINVAL, "max_particles must lie in [1, 2^31-1]");
+    return SOBRC_OK;
+}
+
+// Support of the discrete kernel: d < E/2 with d^2 integer  <=>  d^2 < T.
+int support_T(double E)
+{
+    double r2 = (E / 2.0) * (E / 2.0);
+    int T = (int)ceil(r2);
+    if (T < 1)
+        T = 1;
+    // guard against r2 landing a rounding step away from an integer
+    while (T > 1 && !(sqrt((double)(T - 1)) < E / 2.0))
+        --T;
+    while (sqrt((double)T) < E / 2.0)
+        ++T;
+    return T;
+}
+
+Geom make_geom(const sobrc_params* p)
+{
+    Geom g{};
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->ndim == 3 ? p->nz : 1;
+    g.ndim = p->ndim;
+    if (p->ndim == 3) {
+        g.tsx = g.tsy = g.tsz = 3;  // 8x8x8 voxel tiles
+        g.sy = 10;
+        g.sz = 20;
+        g.mx = g.my = g.mz = 1023u;
+    } else {
+        g.tsx = g.tsy = 4;          // 16x16 pixel tiles
+        g.tsz = 0;
+        g.sy = 16;
+        g.sz = 31;
+        g.mx = g.my = 0xffffu;
+        g.mz = 0u;
+    }
+    g.ntx = (g.nx + (1 << g.tsx) - 1) >> g.tsx;
+    g.nty = (g.ny + (1 << g.tsy) - 1) >> g.tsy;
+    g.ntz = (g.nz + (1 << g.tsz) - 1) >> g.tsz;
+    g.ntiles = g.ntx * g.nty * g.ntz;
+    g.T = support_T(p->E);
+    int h = 0;
+    while ((h + 1) * (h + 1) < g.T)
+        ++h;
+    g.h = h;
+    g.R = p->model == SOBRC_PS ? p->ps_radius : 0;
+    g.R2 = g.R * g.R;
+    g.model = p->model;
+    g.img_u16 = p->image_dtype == SOBRC_U16;
+    g.lambda = (float)p->lambda;
+    g.fx_scale = 1.0;
+    g.fx_inv = 1.0;
+    g.max_labels = p->max_labels;
+    return g;
+}
+
+// W[k] = K(sqrt(k)) of Eq. (5), k < T, computed in FP64 and rounded to fp32.
+void kernel_table(double E, double eps, int T, float* W)
+{
+    for (int k = 0; k < T; ++k) {
+        double u = sqrt((double)k) / E;
+        double v = (1.0 + (u * u - u + 1.0 / 6.0) / (2.0 * eps)) / E;
+        W[k] = (float)v;
+    }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t lab, rec0, rec1, ts0, ts1, act0, act1, tcnt, cand, dE, gH1, st_n, st_s1, flist, W, hist, ds;
+    size_t total;
+};
+
+Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
+{
+    Layout L{};
+    size_t o = 0;
+    long long nvox = (long long)g.nx * g.ny * g.nz;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    L.lab = take((size_t)nvox * 2);
+    L.rec0 = take((size_t)cap * 8);
+    L.rec1 = take((size_t)cap * 8);
+    L.ts0 = take((size_t)(g.ntiles + 1) * 4);
+    L.ts1 = take((size_t)(g.ntiles + 1) * 4);
+    L.act0 = take((size_t)g.ntiles * 4);
+    L.act1 = take((size_t)g.ntiles * 4);
+    L.tcnt = take((size_t)g.ntiles * 4);
+    L.cand = take((size_t)g.ntiles);
+    L.dE = take((size_t)cap * 4);
+    L.gH1 = take((size_t)cap * 4);
+    L.st_n = take((size_t)p->max_labels * 8);
+    L.st_s1 = take((size_t)p->max_labels * 8);
+    L.flist = take((size_t)cap * 8);
+    L.W = take((size_t)kMaxT * 4);
+    L.hist = take((size_t)2 * kHist * 4);
+    L.ds = take(sizeof(DevState));
+    L.total = o;
+    return L;
+}
+
+Bufs carve(const Layout& L, char* base, long long cap)
+{
+    Bufs b{};
+    b.lab = (unsigned short*)(base + L.lab);
+    b.rec[0] = (uint2*)(base + L.rec0);
+    b.rec[1] = (uint2*)(base + L.rec1);
+    b.tstart[0] = (unsigned*)(base + L.ts0);
+    b.tstart[1] = (unsigned*)(base + L.ts1);
+    b.active[0] = (unsigned*)(base + L.act0);
+    b.active[1] = (unsigned*)(base + L.act1);
+    b.tcnt = (unsigned*)(base + L.tcnt);
+    b.cand = (unsigned char*)(base + L.cand);
+    b.dE = (float*)(base + L.dE);
+    b.gH1 = (float*)(base + L.gH1);
+    b.st_n = (long long*)(base + L.st_n);
+    b.st_s1 = (long long*)(base + L.st_s1);
+    b.flist = (uint2*)(base + L.flist);
+    b.W = (float*)(base + L.W);
+    b.hist = (unsigned*)(base + L.hist);
+    b.ds = (DevState*)(base + L.ds);
+    b.cap = (unsigned)cap;
+    return b;
+}
+
+int grid_particles(long long cap)
+{
+    long long g = (cap + kBlock - 1) / kBlock;
+    return (int)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
+}
+
+int grid_tiles(int ntiles)
+{
+    return ntiles < 2048 ? ntiles : 2048;
+}
+
+}  // namespace
+
+struct sobrc_ctx {
+    sobrc_params p;
+    Geom g;
+    Layout L;
+    Bufs b;
+    const void* image = nullptr;
+    int cur = 0;
+    bool initialized = false;
+    int grid_p = 1, grid_t = 1;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;   // pool, pairs
+    std::vector<int> ev_kind;     // kind of each pair
+    size_t ev_used = 0;           // pairs in use
+    double prof_ms[SOBRC_K_NKINDS] = {};
+    long long prof_n[SOBRC_K_NKINDS] = {};
+};
+
+namespace {
+
+constexpr size_t kEventPairs = 8192;
+
+// Launch with optional event pair around it (profiling).
+template <typename F>
+int32_t timed(sobrc_ctx* c, int kind, hipStream_t s, const char* where, F&& launch)
+{
+    bool t = c->prof && c->ev_used < kEventPairs;
+    if (t)
+        SOBRC_HIP(hipEventRecord(c->ev[2 * c->ev_used], s), "hipEventRecord");
+    SOBRC_HIP(launch(), where);
+    if (t) {
+        SOBRC_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s), "hipEventRecord");
+        c->ev_kind[c->ev_used] = kind;
+        ++c->ev_used;
+    }
+    return SOBRC_OK;
+}
+
+#define SOBRC_TRY(expr)            \
+    do {                           \
+        int32_t r_ = (expr);       \
+        if (r_ != SOBRC_OK)        \
+            return r_;             \
+    } while (0)
+
+int32_t read_state(sobrc_ctx* c, DevState* h, hipStream_t s)
+{
+    SOBRC_HIP(hipMemcpyAsync(h, c->b.ds, sizeof(DevState), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return SOBRC_OK;
+}
+
+int32_t status_of(const DevState& h)
+{
+    if (h.err & kErrCapacity)
+        return fail(SOBRC_ECAPACITY, "particle set needs %u entries, capacity exceeded", h.need);
+    if (h.err & kErrLabel)
+        return fail(SOBRC_EINVAL, "label outside [0, max_labels)");
+    return SOBRC_OK;
+}
+
+int32_t launch_step(sobrc_ctx* c, int mode, int32_t* d_nflips, float tol, hipStream_t s)
+{
+    int cur = c->cur, nxt = 1 - cur;
+    const Geom& g = c->g;
+    const Bufs& b = c->b;
+    SOBRC_TRY(timed(c, SOBRC_K_L2DIFF, s, "k_l2diff",
+                    [&] { return launch_l2diff(g, b, c->image, cur, b.dE, 1, c->grid_p, s); }));
+    const float* grad = b.dE;
+    if (mode == SOBRC_MODE_SOBOLEV) {
+        SOBRC_TRY(timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
+                        [&] { return launch_sobolev(g, b, cur, b.dE, b.gH1, 1, c->grid_t, s); }));
+        grad = b.gH1;
+    }
+    SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip",
+                    [&] { return launch_flip(g, b, c->image, cur, grad, c->grid_p, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_COUNT, s, "k_count", [&] { return launch_count(g, b, c->grid_t, 1, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_SCAN, s, "k_scan",
+                    [&] { return launch_scan(g, b, cur, nxt, 0, tol, d_nflips, 1, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_WRITE, s, "k_write",
+                    [&] { return launch_write(g, b, c->image, cur, nxt, c->grid_t, s); }));
+    c->cur = nxt;
+    return SOBRC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* last_error(void) { return g_err; }
+
+int32_t workspace_size(const sobrc_params* params, size_t* bytes)
+{
+    SOBRC_TRY(validate(params));
+    if (!bytes)
+        return fail(SOBRC_EINVAL, "bytes is NULL");
+    Geom g = make_geom(params);
+    *bytes = make_layout(g, params, params->max_particles).total;
+    return SOBRC_OK;
+}
+
+int32_t ctx_create(const sobrc_params* params, void* d_workspace, size_t bytes, sobrc_ctx** out)
+{
+    SOBRC_TRY(validate(params));
+    if (!out)
+        return fail(SOBRC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_workspace)
+        return fail(SOBRC_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_workspace & 255u) != 0)
+        return fail(SOBRC_EINVAL, "workspace must be 256-byte aligned");
+    Geom g = make_geom(params);
+    if (g.T > kMaxT)
+        return fail(SOBRC_EINVAL, "kernel support too large");
+    Layout L = make_layout(g, params, params->max_particles);
+    if (bytes < L.total)
+        return fail(SOBRC_EINVAL, "workspace too small: %zu < %zu bytes", bytes, L.total);
+    sobrc_ctx* c = new (std::nothrow) sobrc_ctx;
+    if (!c)
+        return fail(SOBRC_EINVAL, "out of host memory");
+    c->p = *params;
+    c->g = g;
+    c->L = L;
+    c->b = carve(L, (char*)d_workspace, params->max_particles);
+    c->grid_p = grid_particles(params->max_particles);
+    c->grid_t = grid_tiles(g.ntiles);
+    *out = c;
+    return SOBRC_OK;
+}
+
+int32_t ctx_destroy(sobrc_ctx* ctx)
+{
+    if (!ctx)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    for (hipEvent_t e : ctx->ev)
+        (void)hipEventDestroy(e);
+    delete ctx;
+    return SOBRC_OK;
+}
+
+int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, void* stream)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (!d_image || !d_labels)
+        return fail(SOBRC_EINVAL, "image and labels must be device pointers");
+    hipStream_t s = (hipStream_t)stream;
+    c->initialized = false;
+    c->image = d_image;
+    Geom& g = c->g;
+    const Bufs& b = c->b;
+    // state block, statistics and candidate flags start cleared
+    SOBRC_HIP(hipMemsetAsync(b.ds, 0, sizeof(DevState), s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(b.st_n, 0, (size_t)c->p.max_labels * 8, s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(b.st_s1, 0, (size_t)c->p.max_labels * 8, s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(b.cand, 1, (size_t)g.ntiles, s), "hipMemsetAsync");
+    std::vector<float> W(kMaxT, 0.f);
+    kernel_table(c->p.E, c->p.eps, g.T, W.data());
+    SOBRC_HIP(hipMemcpyAsync(b.W, W.data(), sizeof(float) * kMaxT, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    SOBRC_HIP(launch_init_labels(g, b, d_labels, d_image, s), "k_init_labels");
+    DevState h;
+    SOBRC_TRY(read_state(c, &h, s));
+    if (h.err & kErrLabel)
+        return fail(SOBRC_EINVAL, "label outside [0, %d)", c->p.max_labels);
+    // fixed-point scale of fp32 intensity sums: |sum| < 2^62 over the whole image
+    if (!g.img_u16) {
+        float mx;
+        memcpy(&mx, &h.maxbits, 4);
+        if (!isfinite(mx))
+            return fail(SOBRC_EINVAL, "image contains non-finite values");
+        long long nvox = (long long)g.nx * g.ny * g.nz;
+        double lim = ldexp(1.0, 62) / ((double)nvox * (mx > 0 ? (double)mx : 1.0));
+        int s2 = (int)floor(log2(lim));
+        if (s2 > 60)
+            s2 = 60;
+        if (s2 < -60)
+            s2 = -60;
+        g.fx_scale = ldexp(1.0, s2);
+        g.fx_inv = ldexp(1.0, -s2);
+    }
+    SOBRC_HIP(launch_stats_init(g, b, d_image, s), "k_stats_init");
+    SOBRC_HIP(launch_count(g, b, c->grid_t, 0, s), "k_count");
+    SOBRC_HIP(launch_scan(g, b, 0, 0, 1, 0.f, nullptr, 0, s), "k_scan");
+    SOBRC_HIP(launch_write(g, b, d_image, 0, 0, c->grid_t, s), "k_write");
+    SOBRC_TRY(read_state(c, &h, s));
+    if (h.err & kErrCapacity)
+        return fail(SOBRC_ECAPACITY, "initial particle set needs %u entries > max_particles %lld", h.need,
+                    (long long)c->p.max_particles);
+    c->cur = 0;
+    c->initialized = true;
+    return SOBRC_OK;
+}
+
+int32_t compute_l2_diff(sobrc_ctx* c, float* d_dE_l2, void* stream)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "compute_l2_diff before init_labels");
+    if (!d_dE_l2)
+        return fail(SOBRC_EINVAL, "output is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    return timed(c, SOBRC_K_L2DIFF, s, "k_l2diff",
+                 [&] { return launch_l2diff(c->g, c->b, c->image, c->cur, d_dE_l2, 0, c->grid_p, s); });
+}
+
+int32_t sobolev_smooth(sobrc_ctx* c, const float* d_in, float* d_out, void* stream)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "sobolev_smooth before init_labels");
+    if (!d_in || !d_out)
+        return fail(SOBRC_EINVAL, "input and output must be device pointers");
+    if (d_in == d_out)
+        return fail(SOBRC_EINVAL, "input and output must be distinct buffers (Jacobi update)");
+    hipStream_t s = (hipStream_t)stream;
+    return timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
+                 [&] { return launch_sobolev(c->g, c->b, c->cur, d_in, d_out, 0, c->grid_t, s); });
+}
+
+int32_t step(sobrc_ctx* c, int32_t mode, int32_t* d_nflips, void* stream)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "step before init_labels");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV or SOBRC_MODE_L2");
+    return launch_step(c, mode, d_nflips, 0.f, (hipStream_t)stream);
+}
+
+int32_t run(sobrc_ctx* c, int32_t max_iters, double flip_tol, int32_t mode, int32_t* h_iters_done, void* stream)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "run before init_labels");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV or SOBRC_MODE_L2");
+    if (max_iters < 0 || !(flip_tol >= 0.0))
+        return fail(SOBRC_EINVAL, "max_iters must be >= 0 and flip_tol >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    DevState h;
+    SOBRC_TRY(read_state(c, &h, s));
+    SOBRC_TRY(status_of(h));
+    unsigned it0 = h.iters;
+    // a previous run may have stopped on its tolerance: start afresh
+    SOBRC_HIP(hipMemsetAsync(&c->b.ds->converged, 0, sizeof(unsigned), s), "hipMemsetAsync");
+    for (int t = 0; t < max_iters; ++t)
+        SOBRC_TRY(launch_step(c, mode, nullptr, (float)flip_tol, s));
+    SOBRC_TRY(read_state(c, &h, s));
+    if (h_iters_done)
+        *h_iters_done = (int32_t)(h.iters - it0);
+    return status_of(h);
+}
+
+int32_t ctx_sync(sobrc_ctx* c, void* stream)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "ctx_sync before init_labels");
+    DevState h;
+    SOBRC_TRY(read_state(c, &h, (hipStream_t)stream));
+    return status_of(h);
+}
+
+int32_t get_particles(sobrc_ctx* c, int64_t* h_n, int32_t* d_lin, int32_t* d_a, int32_t* d_b, void* stream)
+{
+    if (!c || !h_n)
+        return fail(SOBRC_EINVAL, "ctx and h_n must be non-NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "get_particles before init_labels");
+    hipStream_t s = (hipStream_t)stream;
+    DevState h;
+    SOBRC_TRY(read_state(c, &h, s));
+    *h_n = h.n[c->cur];
+    if (d_lin || d_a || d_b)
+        SOBRC_HIP(launch_unpack(c->g, c->b, c->cur, d_lin, d_a, d_b, s), "k_unpack");
+    return status_of(h);
+}
+
+int32_t get_labels(sobrc_ctx* c, int32_t* d_labels, void* stream)
+{
+    if (!c || !d_labels)
+        return fail(SOBRC_EINVAL, "ctx and labels must be non-NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "get_labels before init_labels");
+    SOBRC_HIP(launch_labels_out(c->g, c->b, d_labels, (hipStream_t)stream), "k_labels_out");
+    return SOBRC_OK;
+}
+
+int32_t get_region_stats(sobrc_ctx* c, int64_t* h_count, double* h_sum, void* stream)
+{
+    if (!c || !h_count)
+        return fail(SOBRC_EINVAL, "ctx and h_count must be non-NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "get_region_stats before init_labels");
+    hipStream_t s = (hipStream_t)stream;
+    int M = c->p.max_labels;
+    std::vector<long long> n(M), s1(M);
+    SOBRC_HIP(hipMemcpyAsync(n.data(), c->b.st_n, 8 * (size_t)M, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipMemcpyAsync(s1.data(), c->b.st_s1, 8 * (size_t)M, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int l = 0; l < M; ++l) {
+        h_count[l] = n[l];
+        if (h_sum)
+            h_sum[l] = (double)s1[l] * c->g.fx_inv;
+    }
+    return SOBRC_OK;
+}
+
+int32_t get_history(sobrc_ctx* c, int32_t cap, int32_t* h_n, int32_t* h_flips, int32_t* h_len, void* stream)
+{
+    if (!c || !h_len || cap < 0 || (cap > 0 && (!h_n || !h_flips)))
+        return fail(SOBRC_EINVAL, "bad arguments to get_history");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "get_history before init_labels");
+    hipStream_t s = (hipStream_t)stream;
+    DevState h;
+    SOBRC_TRY(read_state(c, &h, s));
+    std::vector<unsigned> hist(2 * kHist);
+    SOBRC_HIP(hipMemcpyAsync(hist.data(), c->b.hist, 8 * (size_t)kHist, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    unsigned avail = h.iters < (unsigned)kHist ? h.iters : (unsigned)kHist;
+    unsigned take = (unsigned)cap < avail ? (unsigned)cap : avail;
+    for (unsigned k = 0; k < take; ++k) {
+        unsigned it = h.iters - take + k;
+        h_n[k] = (int32_t)hist[it % kHist];
+        h_flips[k] = (int32_t)hist[kHist + it % kHist];
+    }
+    *h_len = (int32_t)take;
+    return SOBRC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------- stateless Eq. (6) on given particles
+
+namespace {
+struct PLayout {
+    size_t ts, act, tcnt, fill, rec, vin, vout, origin, W, ds, total;
+};
+PLayout make_playout(const Geom& g, long long n)
+{
+    PLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    long long m = n > 0 ? n : 1;
+    L.ts = take((size_t)(g.ntiles + 1) * 4);
+    L.act = take((size_t)g.ntiles * 4);
+    L.tcnt = take((size_t)g.ntiles * 4);
+    L.fill = take((size_t)g.ntiles * 4);
+    L.rec = take((size_t)m * 8);
+    L.vin = take((size_t)m * 4);
+    L.vout = take((size_t)m * 4);
+    L.origin = take((size_t)m * 4);
+    L.W = take((size_t)kMaxT * 4);
+    L.ds = take(sizeof(DevState));
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t sobolev_particles_workspace_size(const sobrc_params* params, int64_t n, size_t* bytes)
+{
+    sobrc_params q = *params;
+    q.max_particles = 1;
+    SOBRC_TRY(validate(&q));
+    if (!bytes || n < 0 || n > 0x7fffffffLL)
+        return fail(SOBRC_EINVAL, "bad particle count or NULL bytes");
+    *bytes = make_playout(make_geom(params), n).total;
+    return SOBRC_OK;
+}
+
+int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const int32_t* d_lin, const int32_t* d_a,
+                                 const int32_t* d_b, const float* d_in, float* d_out, void* d_ws, size_t ws_bytes,
+                                 void* stream)
+{
+    if (!params)
+        return fail(SOBRC_EINVAL, "params is NULL");
+    sobrc_params q = *params;
+    q.max_particles = 1;
+    SOBRC_TRY(validate(&q));
+    if (n < 0 || n > 0x7fffffffLL)
+        return fail(SOBRC_EINVAL, "particle count out of range");
+    if (n == 0)
+        return SOBRC_OK;
+    if (!d_lin || !d_a || !d_b || !d_in || !d_out || !d_ws)
+        return fail(SOBRC_EINVAL, "NULL device pointer");
+    if (((uintptr_t)d_ws & 255u) != 0)
+        return fail(SOBRC_EINVAL, "workspace must be 256-byte aligned");
+    Geom g = make_geom(params);
+    if (g.T > kMaxT)
+        return fail(SOBRC_EINVAL, "kernel support too large");
+    PLayout L = make_playout(g, n);
+    if (ws_bytes < L.total)
+        return fail(SOBRC_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    char* base = (char*)d_ws;
+    Bufs b{};
+    b.tstart[0] = b.tstart[1] = (unsigned*)(base + L.ts);
+    b.active[0] = b.active[1] = (unsigned*)(base + L.act);
+    b.tcnt = (unsigned*)(base + L.tcnt);
+    b.rec[0] = b.rec[1] = (uint2*)(base + L.rec);
+    b.dE = (float*)(base + L.vin);
+    b.gH1 = (float*)(base + L.vout);
+    b.W = (float*)(base + L.W);
+    b.ds = (DevState*)(base + L.ds);
+    b.cap = (unsigned)n;
+    unsigned* fill = (unsigned*)(base + L.fill);
+    unsigned* origin = (unsigned*)(base + L.origin);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> W(kMaxT, 0.f);
+    kernel_table(params->E, params->eps, g.T, W.data());
+    SOBRC_HIP(hipMemcpyAsync(b.W, W.data(), sizeof(float) * kMaxT, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipMemsetAsync(b.ds, 0, sizeof(DevState), s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(b.tcnt, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(fill, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
+    SOBRC_HIP(launch_bin_count(g, b, n, d_lin, d_a, d_b, s), "k_bin_count");
+    DevState h;
+    SOBRC_HIP(hipMemcpyAsync(&h, b.ds, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (h.err & kErrInput)
+        return fail(SOBRC_EINVAL, "particle outside the image or with a bad label pair");
+    SOBRC_HIP(launch_scan(g, b, 0, 0, 1, 0.f, nullptr, 0, s), "k_scan");
+    SOBRC_HIP(launch_bin_scatter(g, b, n, d_lin, d_a, d_b, d_in, fill, origin, s), "k_bin_scatter");
+    SOBRC_HIP(launch_sobolev(g, b, 0, b.dE, b.gH1, 0, grid_tiles(g.ntiles), s), "k_sobolev");
+    SOBRC_HIP(launch_unbin(b, n, origin, b.gH1, d_out, s), "k_unbin");
+    return SOBRC_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+int32_t profile_enable(sobrc_ctx* c, int32_t on)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (on && c->ev.empty()) {
+        try {
+            c->ev.resize(2 * kEventPairs);
+            c->ev_kind.resize(kEventPairs);
+        } catch (...) {
+            return fail(SOBRC_EINVAL, "out of host memory");
+        }
+        for (auto& e : c->ev)
+            SOBRC_HIP(hipEventCreate(&e), "hipEventCreate");
+    }
+    c->prof = on != 0;
+    return SOBRC_OK;
+}
+
+int32_t profile_read(sobrc_ctx* c, double* h_ms, int64_t* h_launches, int32_t reset)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    for (size_t k = 0; k < c->ev_used; ++k) {
+        SOBRC_HIP(hipEventSynchronize(c->ev[2 * k + 1]), "hipEventSynchronize");
+        float ms = 0.f;
+        SOBRC_HIP(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]), "hipEventElapsedTime");
+        c->prof_ms[c->ev_kind[k]] += ms;
+        c->prof_n[c->ev_kind[k]] += 1;
+    }
+    c->ev_used = 0;
+    for (int k = 0; k < SOBRC_K_NKINDS; ++k) {
+        if (h_ms)
+            h_ms[k] = c->prof_ms[k];
+        if (h_launches)
+            h_launches[k] = c->prof_n[k];
+        if (reset) {
+            c->prof_ms[k] = 0.0;
+            c->prof_n[k] = 0;
+        }
+    }
+    return SOBRC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// sobrc_dev.h -- internal types shared by the HIP kernels and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sobrc {
+
+constexpr int kBlock = 256;        // threads per block of the particle/tile kernels
+constexpr int kScanThreads = 1024; // single-block tile scan
+constexpr int kHist = 4096;        // telemetry ring (iterations)
+constexpr int kStageCap = 2048;    // staged neighbour particles per round (k_sobolev)
+constexpr int kMaxT = 1024;        // support table entries: d^2 < T <= (E/2)^2 rounded up
+
+// error bits kept on the device (sticky until init_labels)
+constexpr unsigned kErrCapacity = 1u;
+constexpr unsigned kErrLabel = 2u;
+constexpr unsigned kErrInput = 4u;
+
+// Problem geometry and parameters, passed by value to every kernel.
+struct Geom {
+    int nx, ny, nz, ndim;
+    int tsx, tsy, tsz;          // log2 of the tile edge per axis
+    int ntx, nty, ntz, ntiles;  // tiles per axis, total
+    int sy, sz;                 // particle position packing: x | y << sy | z << sz
+    unsigned mx, my, mz;        // field masks after shifting
+    int T;                      // Sobolev support: integer d^2 < T  <=>  d < E/2
+    int h;                      // largest axis offset k with k*k < T
+    int R, R2;                  // PS ball radius and radius^2
+    int model;                  // 0 PC, 1 PS
+    int img_u16;                // image element type
+    float lambda;
+    double fx_scale;            // fixed-point scale of intensity sums (2^s)
+    double fx_inv;              // 1 / fx_scale
+    int max_labels;
+};
+
+// Device-resident control block of a context.
+struct DevState {
+    unsigned n[2];          // particle count of state buffer 0/1
+    unsigned n_active[2];   // non-empty tiles of state buffer 0/1
+    unsigned nflips;        // pixels changed by the running step
+    unsigned nflip_list;    // entries in the flip list of the running step
+    unsigned err;           // sticky error bits
+    unsigned undo;          // running step overflowed: roll back in k_write
+    unsigned go;            // running step passed k_scan and commits in k_write
+    unsigned need;          // particle count that did not fit
+    unsigned converged;     // flip tolerance reached: further steps do nothing
+    unsigned iters;         // steps committed
+    unsigned maxbits;       // init: bit pattern of max |I| (fp32 images)
+    unsigned pad[3];
+};
+
+// Device pointers of one context (all carved from the caller's workspace).
+struct Bufs {
+    unsigned short* lab;     // label field, nvox
+    uint2* rec[2];           // particle records {pos, a | b << 16}, capacity each
+    unsigned* tstart[2];     // tile_start, ntiles + 1 each
+    unsigned* active[2];     // non-empty tiles, ntiles each
+    unsigned* tcnt;          // per-tile particle count of the next state
+    unsigned char* cand;     // tiles to scan for particles in the next emission
+    float* dE;               // L2 gradient, capacity
+    float* gH1;              // Sobolev gradient, capacity
+    long long* st_n;         // region pixel counts, max_labels
+    long long* st_s1;        // region intensity sums (fixed point), max_labels
+    uint2* flist;            // flips of the running step {lin, a | b << 16}
+    float* W;                // kernel table W[d^2], T entries
+    unsigned* hist;          // 2 * kHist: N_t and flips_t
+    DevState* ds;
+    unsigned cap;
+};
+
+// Host wrappers around kernel launches (defined in sobrc_kernels.hip).
+hipError_t launch_init_labels(const Geom& g, const Bufs& b, const int32_t* labels_in,
+                              const void* img, hipStream_t s);
+hipError_t launch_stats_init(const Geom& g, const Bufs& b, const void* img, hipStream_t s);
+hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur, float* out,
+                         int gated, int grid, hipStream_t s);
+hipError_t launch_sobolev(const Geom& g, const Bufs& b, int cur, const float* in, float* out,
+                          int gated, int grid, hipStream_t s);
+hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,
+                       int grid, hipStream_t s);
+hipError_t launch_count(const Geom& g, const Bufs& b, int grid, int gated, hipStream_t s);
+hipError_t launch_scan(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol,
+                       int32_t* d_nflips, int gated, hipStream_t s);
+hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, int nxt, int grid,
+                        hipStream_t s);
+hipError_t launch_unpack(const Geom& g, const Bufs& b, int cur, int32_t* lin, int32_t* a,
+                         int32_t* bb, hipStream_t s);
+hipError_t launch_labels_out(const Geom& g, const Bufs& b, int32_t* out, hipStream_t s);
+
+// Stateless binning for sobolev_smooth_particles.
+hipError_t launch_bin_count(const Geom& g, const Bufs& b, long long n, const int32_t* lin,
+                            const int32_t* a, const int32_t* bb, hipStream_t s);
+hipError_t launch_bin_scatter(const Geom& g, const Bufs& b, long long n, const int32_t* lin,
+                              const int32_t* a, const int32_t* bb, const float* in,
+                              unsigned* fill, unsigned* origin, hipStream_t s);
+hipError_t launch_unbin(const Bufs& b, long long n, const unsigned* origin, const float* binned,
+                        float* out, hipStream_t s);
+
+}  // namespace sobrc

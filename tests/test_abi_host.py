@@ -1,0 +1,104 @@
+"""C-ABI contract checks that run without a GPU: the library loads, exports
+every function include/sobrc.h declares, and rejects bad parameters and call
+orders on the host before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1403_0240_amd import sobrc as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sobrc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int32_t|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(S.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return S.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(S.EXPORTS)
+
+
+def _p(**kw):
+    p = S.make_params((64, 48), "float32", 8.0, 0.1, max_particles=1000)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [dict(ndim=4), dict(nx=0), dict(ny=40000), dict(nz=2),
+                                dict(image_dtype=7), dict(model=3), dict(model=S.PS, ps_radius=1),
+                                dict(E=0.0), dict(E=65.0), dict(eps=0.0), dict(lam=-1.0),
+                                dict(max_labels=1), dict(max_labels=65536), dict(max_particles=0)])
+def test_bad_params(L, kw):
+    n = C.c_size_t(0)
+    assert L.workspace_size(C.byref(_p(**kw)), C.byref(n)) == S.EINVAL
+    assert L.last_error()
+
+
+def test_3d_limits(L):
+    p = S.make_params((8, 2000, 16), "uint16", 6.0, 1.0)
+    assert L.workspace_size(C.byref(p), C.byref(C.c_size_t())) == S.EINVAL
+    p = S.make_params((1024, 1024, 1024), "uint16", 6.0, 1.0, max_particles=1 << 24)
+    n = C.c_size_t(0)
+    assert L.workspace_size(C.byref(p), C.byref(n)) == S.OK
+    assert n.value > 2 * 1024 ** 3  # u16 label field
+
+
+def test_workspace_grows_with_capacity(L):
+    a, b = C.c_size_t(0), C.c_size_t(0)
+    assert L.workspace_size(C.byref(_p(max_particles=1000)), C.byref(a)) == 0
+    assert L.workspace_size(C.byref(_p(max_particles=100000)), C.byref(b)) == 0
+    assert b.value - a.value >= 99000 * 31  # records x2, gradients x2, flip list
+
+
+def test_call_order_and_nulls(L):
+    p = _p()
+    n = C.c_size_t(0)
+    assert L.workspace_size(C.byref(p), C.byref(n)) == 0
+    h = C.c_void_p(0)
+    fake = C.c_void_p(1 << 20)  # never dereferenced: ctx_create makes no device call
+    assert L.ctx_create(C.byref(p), None, n.value, C.byref(h)) == S.EINVAL
+    assert L.ctx_create(C.byref(p), C.c_void_p((1 << 20) + 4), n.value, C.byref(h)) == S.EINVAL
+    assert L.ctx_create(C.byref(p), fake, n.value - 1, C.byref(h)) == S.EINVAL
+    assert L.ctx_create(C.byref(p), fake, n.value, C.byref(h)) == S.OK
+    try:
+        assert L.step(h, S.MODE_SOBOLEV, None, None) == S.ESTATE
+        assert L.run(h, 3, 0.0, S.MODE_SOBOLEV, None, None) == S.ESTATE
+        assert L.compute_l2_diff(h, fake, None) == S.ESTATE
+        assert L.sobolev_smooth(h, fake, fake, None) == S.ESTATE
+        assert L.get_labels(h, fake, None) == S.ESTATE
+        assert L.get_particles(h, C.byref(C.c_int64()), None, None, None, None) == S.ESTATE
+        assert L.ctx_sync(h, None) == S.ESTATE
+        assert L.init_labels(h, None, fake, None) == S.EINVAL
+        assert L.init_labels(None, fake, fake, None) == S.EINVAL
+        assert L.last_error()
+    finally:
+        assert L.ctx_destroy(h) == S.OK
+    assert L.ctx_destroy(None) == S.EINVAL
+
+
+def test_stateless_validation(L):
+    p = _p()
+    n = C.c_size_t(0)
+    assert L.sobolev_particles_workspace_size(C.byref(p), -1, C.byref(n)) == S.EINVAL
+    assert L.sobolev_particles_workspace_size(C.byref(p), 10, C.byref(n)) == S.OK
+    # zero particles: nothing to do, no device call
+    assert L.sobolev_smooth_particles(C.byref(p), 0, None, None, None, None, None, None, 0, None) == S.OK
+    fake = C.c_void_p(1 << 20)
+    assert L.sobolev_smooth_particles(C.byref(p), 10, fake, fake, fake, fake, fake, fake, 16, None) == S.EINVAL

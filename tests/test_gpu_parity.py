@@ -1,0 +1,354 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (stated once here, used throughout):
+  * particle sets and all integer bookkeeping: bit-exact;
+  * L2 and Sobolev gradients: max |gpu - oracle| <= 1e-5 * max |oracle|
+    (fp32 arithmetic against FP64; the Sobolev bar is the target accuracy of
+    the method's gradient evaluation);
+  * labels after a step: identical at every pixel whose decision is not
+    marginal; a pixel is marginal if one of its particles has
+    |g| <= 1e-4 * max |g| or two of its negative gradients lie within that
+    margin of each other.  Marginal flips are counted and printed.
+Every input comes from the seeded generators; every expected value from the
+oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1403_0240_amd import sobrc as S  # noqa: E402
+from paper_1403_0240_amd import workloads as W  # noqa: E402
+
+REL_GRAD = 1e-5
+MARGIN = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S.lib()
+
+
+def _keys(lin, b):
+    return np.asarray(lin, np.int64) * 65536 + np.asarray(b, np.int64)
+
+
+def gpu_state(w, cap=None):
+    ctx, img, lab = S.from_workload(w, max_particles=cap)
+    S.init_labels(ctx, img, lab)
+    return ctx, img, lab
+
+
+def gpu_particles(ctx):
+    lin, a, b = (t.cpu().numpy() for t in S.get_particles(ctx))
+    return lin.astype(np.int64), a, b
+
+
+def match_order(ctx, lin_o, b_o):
+    """Permutation taking GPU (context) order to oracle order; asserts the two
+    particle sets are identical."""
+    lin, a, b = gpu_particles(ctx)
+    gk = _keys(lin, b)
+    perm = np.argsort(gk, kind="stable")
+    ok = _keys(lin_o, b_o)
+    assert len(gk) == len(ok), f"particle count {len(gk)} != oracle {len(ok)}"
+    assert np.array_equal(gk[perm], ok), "particle sets differ"
+    return perm, lin, a, b
+
+
+def rel_err(g, o):
+    scale = np.abs(o).max() if len(o) else 1.0
+    return float(np.abs(g - o).max() / scale) if len(o) else 0.0
+
+
+def marginal_pixels(lin, g, thr):
+    lin = np.asarray(lin)
+    m = set(lin[np.abs(g) <= thr].tolist())
+    order = np.lexsort((g, lin))
+    ls, gs = lin[order], g[order]
+    for k in range(1, len(ls)):
+        if ls[k] == ls[k - 1] and gs[k - 1] < 0 and gs[k] - gs[k - 1] <= thr:
+            m.add(int(ls[k]))
+    return m
+
+
+def compare_labels(L_gpu, L_ora, lin, g):
+    """Labels agree at all non-marginal pixels; returns the marginal flips."""
+    thr = MARGIN * (np.abs(g).max() if len(g) else 1.0)
+    marg = marginal_pixels(lin, g, thr)
+    diff = np.flatnonzero(L_gpu.reshape(-1) != L_ora.reshape(-1))
+    bad = [int(i) for i in diff if int(i) not in marg]
+    assert not bad, f"{len(bad)} non-marginal pixels differ, e.g. {bad[:5]}"
+    return len(diff)
+
+
+CASES = {
+    "rand2d_blobs": lambda: W.random_multilabel(0, (37, 45), 3, E=6.0, lam=0.4),
+    "rand2d_noise4": lambda: W.random_multilabel(1, (23, 29), 4, blobs=False, E=8.0, lam=0.3),
+    "rand3d_blobs": lambda: W.random_multilabel(2, (13, 17, 19), 3, E=6.0, lam=0.5),
+    "rand3d_noise": lambda: W.random_multilabel(3, (9, 11, 10), 3, blobs=False, E=5.0, lam=0.2),
+    "rand3d_u16": lambda: W.random_multilabel(4, (12, 20, 9), 3, dtype=np.uint16, E=6.0, lam=30.0),
+    "rand2d_ps": lambda: W.random_multilabel(5, (40, 33), 3, E=8.0, lam=0.2, model=W.PS, ps_radius=3),
+    "rand3d_ps": lambda: W.random_multilabel(6, (11, 14, 13), 2, E=6.0, lam=0.2, model=W.PS, ps_radius=2),
+    "disk2d_128": lambda: W.disk2d(),
+    "half_plane_3d": lambda: W.half_plane((20, 21, 22), 9, axis=1, E=6.0),
+    "wide_kernel_2d": lambda: W.random_multilabel(7, (70, 50), 2, E=40.0, lam=0.1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_particles_and_gradients(ora, name):
+    w = CASES[name]()
+    print(f"[case {name} shape={w.image.shape}]", flush=True)
+    P = ora.params_of(w)
+    ctx, img, lab = gpu_state(w)
+    lin_o, a_o, b_o = ora.particles(P, w.labels)
+    perm, lin, a, b = match_order(ctx, lin_o, b_o)
+    assert np.array_equal(a[perm], a_o)
+    # context order: tile-major, then position inside the tile, then b
+    # L2 gradient
+    dl2 = S.compute_l2_diff(ctx)[: len(lin)].cpu().numpy()
+    o_l2 = ora.l2diff(P, w.image, w.labels, lin_o, a_o, b_o)
+    assert rel_err(dl2[perm], o_l2) <= REL_GRAD
+    # Sobolev gradient of the L2 gradients each side computed itself
+    dh1 = S.sobolev_smooth(ctx, S.compute_l2_diff(ctx))[: len(lin)].cpu().numpy()
+    o_h1 = ora.sobolev(P, lin_o, a_o, b_o, o_l2)
+    assert rel_err(dh1[perm], o_h1) <= REL_GRAD
+    # Sobolev update of seeded random inputs (isolates Eq. (6))
+    vals = np.random.default_rng(11).normal(size=len(lin_o))
+    inp = torch.zeros(ctx.params.max_particles, dtype=torch.float32, device="cuda")
+    rank = np.empty_like(perm)
+    rank[perm] = np.arange(len(perm))
+    inp[: len(lin)] = torch.from_numpy(vals[rank].astype(np.float32)).cuda()
+    out = S.sobolev_smooth(ctx, inp)[: len(lin)].cpu().numpy()
+    o_r = ora.sobolev(P, lin_o, a_o, b_o, vals.astype(np.float32).astype(np.float64),
+                      neigh=ora.NEIGH_BRUTE)
+    assert rel_err(out[perm], o_r) <= REL_GRAD
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_step_trajectory(ora, name):
+    """Independent GPU and oracle trajectories: particle sets, statistics and
+    labels agree after every step until the first marginal flip (each side
+    evolves from its own state, so a marginal flip is where comparison ends)."""
+    w = CASES[name]()
+    print(f"[case {name} shape={w.image.shape}]", flush=True)
+    P = ora.params_of(w)
+    ctx, img, lab = gpu_state(w)
+    L_o = w.labels.copy()
+    nfl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    steps = 12
+    for t in range(steps):
+        L_next, info = ora.step(P, w.image, L_o, ora.MODE_SOBOLEV)
+        match_order(ctx, info["lin"], info["b"])
+        S.step(ctx, S.MODE_SOBOLEV, nfl)
+        L_g = S.get_labels(ctx).cpu().numpy()
+        nd = compare_labels(L_g, L_next, info["lin"], info["dE_h1"])
+        if nd:
+            print(f"  step {t}: {nd} marginal flips differ; stopping comparison")
+            return
+        assert int(nfl.item()) == info["flips"]
+        n_g, s_g = S.get_region_stats(ctx)
+        n_o, s1_o, _ = ora.region_stats(P, w.image, L_next)
+        assert np.array_equal(n_g, n_o)
+        if w.image.dtype == np.uint16:
+            assert np.array_equal(s_g, s1_o)
+        else:
+            assert np.allclose(s_g, s1_o, rtol=0, atol=1e-6 * max(1.0, np.abs(s1_o).max()))
+        L_o = L_next
+    lin_o, a_o, b_o = ora.particles(P, L_o)
+    match_order(ctx, lin_o, b_o)
+    hn, hf = S.get_history(ctx)
+    assert len(hn) == steps
+
+
+def test_l2_mode_and_tolerance_stop(ora):
+    w = W.disk2d()
+    P = ora.params_of(w)
+    L_o, t_o, hn, hf = ora.run(P, w.image, w.labels, mode=ora.MODE_L2, max_iters=200, tol=1e-3)
+    ctx, img, lab = gpu_state(w)
+    t_g = S.run(ctx, 200, 1e-3, S.MODE_L2)
+    L_g = S.get_labels(ctx).cpu().numpy()
+    if (L_g != L_o).any():
+        pytest.skip("trajectories split at a marginal flip")
+    assert t_g == t_o
+    gn, gf = S.get_history(ctx)
+    assert np.array_equal(gn, hn) and np.array_equal(gf, hf)
+    # further steps after convergence keep working (run resets the stop flag)
+    assert S.run(ctx, 3, 0.0, S.MODE_L2) == 3
+
+
+def test_degenerate_support_equals_l2_step(ora):
+    w = W.random_multilabel(8, (31, 26), 3, E=2.0, lam=0.3)
+    ctx1, _, _ = gpu_state(w)
+    ctx2, _, _ = gpu_state(w)
+    for _ in range(5):
+        S.step(ctx1, S.MODE_SOBOLEV)
+        S.step(ctx2, S.MODE_L2)
+    assert torch.equal(S.get_labels(ctx1), S.get_labels(ctx2))
+    dl2 = S.compute_l2_diff(ctx1)
+    dh1 = S.sobolev_smooth(ctx1, dl2)
+    n = S.particle_count(ctx1)
+    assert torch.allclose(dh1[:n], 1.5 * dl2[:n], rtol=1e-6, atol=0)
+
+
+def test_straight_edge_invariant_gpu(ora):
+    """Constant inputs on a straight 3D plane: every interior particle gets
+    c*wbar - c'*wbar' (same value as the oracle, bit-independent)."""
+    w = W.half_plane((24, 24, 24), 12, axis=0, E=6.0)
+    P = ora.params_of(w)
+    ctx, _, _ = gpu_state(w)
+    lin, a, b = gpu_particles(ctx)
+    vals = np.where(a == 1, 3.0, -2.0).astype(np.float32)
+    inp = torch.zeros(ctx.params.max_particles, dtype=torch.float32, device="cuda")
+    inp[: len(lin)] = torch.from_numpy(vals).cuda()
+    out = S.sobolev_smooth(ctx, inp)[: len(lin)].cpu().numpy()
+    o = ora.sobolev(P, lin, a, b, vals.astype(np.float64))
+    assert rel_err(out, o) <= REL_GRAD
+    x, y = lin % 24, (lin // 24) % 24
+    inner = (x >= 3) & (x < 21) & (y >= 3) & (y < 21)
+    for side in (0, 1):
+        v = out[inner & (a == side)]
+        assert np.ptp(v) <= 1e-6 * np.abs(v).max()
+
+
+def test_stateless_sobolev_particles(ora):
+    rng = np.random.default_rng(3)
+    for shape, E in (((50, 60), 8.0), ((15, 18, 21), 6.0)):
+        w = W.random_multilabel(9, shape, 3, E=E)
+        P = ora.params_of(w)
+        lin, a, b = ora.particles(P, w.labels)
+        perm = rng.permutation(len(lin))
+        lin, a, b = lin[perm], a[perm], b[perm]
+        vals = rng.normal(size=len(lin)).astype(np.float32)
+        p = S.make_params(shape, "float32", E, 0.0, max_labels=3)
+        out = S.sobolev_smooth_particles(
+            p, torch.from_numpy(lin.astype(np.int32)).cuda(), torch.from_numpy(a).cuda(),
+            torch.from_numpy(b).cuda(), torch.from_numpy(vals).cuda()).cpu().numpy()
+        o = ora.sobolev(P, lin, a, b, vals.astype(np.float64))
+        assert rel_err(out, o) <= REL_GRAD
+    with pytest.raises(S.SobrcError):
+        bad = torch.tensor([0, 10 ** 7], dtype=torch.int32, device="cuda")
+        z = torch.zeros(2, dtype=torch.int32, device="cuda")
+        S.sobolev_smooth_particles(p, bad, z, z + 1, torch.zeros(2, device="cuda"))
+
+
+def test_label_range_error():
+    w = W.disk2d()
+    w.labels[3, 3] = 7
+    ctx, img, lab = S.from_workload(w)
+    with pytest.raises(S.SobrcError) as e:
+        S.init_labels(ctx, img, lab)
+    assert e.value.code == S.EINVAL
+    with pytest.raises(S.SobrcError) as e:
+        S.step(ctx)
+    assert e.value.code == S.ESTATE
+
+
+def test_capacity_errors_roll_back(ora):
+    w = W.disk2d()
+    ctx, img, lab = S.from_workload(w, max_particles=100)
+    with pytest.raises(S.SobrcError) as e:
+        S.init_labels(ctx, img, lab)
+    assert e.value.code == S.ECAPACITY
+    # room for the initial 324 particles but not for the grown contour
+    ctx, img, lab = S.from_workload(w, max_particles=330)
+    S.init_labels(ctx, img, lab)
+    lin0, a0, b0 = gpu_particles(ctx)
+    S.step(ctx)
+    with pytest.raises(S.SobrcError) as e:
+        S.ctx_sync(ctx)
+    assert e.value.code == S.ECAPACITY
+    assert (S.get_labels(ctx).cpu().numpy() == w.labels).all()
+    S.step(ctx)  # further steps do nothing
+    lin1, a1, b1 = gpu_particles_unchecked(ctx)
+    assert np.array_equal(lin0, lin1) and np.array_equal(b0, b1)
+    n_g, _ = S.get_region_stats(ctx)
+    assert n_g[1] == (w.labels == 1).sum()
+    # a new init_labels clears the error
+    ctx2, img2, lab2 = S.from_workload(w)
+    S.init_labels(ctx2, img2, lab2)
+    S.step(ctx2)
+    S.ctx_sync(ctx2)
+
+
+def gpu_particles_unchecked(ctx):
+    import ctypes as C
+    n = C.c_int64(0)
+    S.lib().get_particles(ctx.handle, C.byref(n), None, None, None, None)
+    lin = torch.empty(n.value, dtype=torch.int32, device="cuda")
+    a, b = torch.empty_like(lin), torch.empty_like(lin)
+    S.lib().get_particles(ctx.handle, C.byref(n), S._ptr(lin), S._ptr(a), S._ptr(b), None)
+    torch.cuda.synchronize()
+    return lin.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy()
+
+
+def test_determinism_and_resume():
+    w = W.random_multilabel(10, (64, 80), 3, E=8.0, lam=0.3)
+    outs = []
+    for _ in range(2):
+        ctx, img, lab = gpu_state(w)
+        S.run(ctx, 15, 0.0, S.MODE_SOBOLEV)
+        dl2 = S.compute_l2_diff(ctx)
+        dh1 = S.sobolev_smooth(ctx, dl2)
+        n = S.particle_count(ctx)
+        outs.append((S.get_labels(ctx).cpu(), S.get_particles(ctx)[0].cpu(), dh1[:n].cpu()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][2], outs[1][2])
+    # checkpoint/resume: 9 iterations, restart from the saved labels, 6 more
+    ctx, img, lab = gpu_state(w)
+    S.run(ctx, 9, 0.0, S.MODE_SOBOLEV)
+    saved = S.get_labels(ctx).clone()
+    ctx2, _, _ = S.from_workload(w)
+    S.init_labels(ctx2, img, saved)
+    S.run(ctx2, 6, 0.0, S.MODE_SOBOLEV)
+    assert torch.equal(S.get_labels(ctx2).cpu(), outs[0][0])
+
+
+def test_uniform_and_empty_fields(ora):
+    w = W.random_multilabel(12, (20, 16), 2)
+    w.labels[:] = 1
+    ctx, img, lab = gpu_state(w)
+    assert S.particle_count(ctx) == 0
+    assert S.run(ctx, 4, 0.0, S.MODE_SOBOLEV) == 4
+    assert (S.get_labels(ctx).cpu().numpy() == 1).all()
+    # 1-pixel-wide and single-voxel-deep volumes
+    for shape in ((1, 30), (30, 1), (1, 1, 17), (5, 1, 9)):
+        w = W.random_multilabel(13, shape, 3, blobs=False, E=6.0)
+        P = ora.params_of(w)
+        ctx, _, _ = gpu_state(w)
+        lin_o, a_o, b_o = ora.particles(P, w.labels)
+        match_order(ctx, lin_o, b_o)
+        L_next, info = ora.step(P, w.image, w.labels)
+        S.step(ctx)
+        compare_labels(S.get_labels(ctx).cpu().numpy(), L_next, info["lin"], info["dE_h1"])
+
+
+@pytest.mark.parametrize("name", ["ellipsoids3d_256", "ellipses2d_1024"])
+def test_full_size_first_step(ora, name):
+    """The full-size workloads in the launch configuration the benchmark uses:
+    particle set bit-exact, gradients within the bar on every particle (L2)
+    and on a sample (Sobolev, evaluated one by one in the oracle), labels after
+    one step identical outside the margin."""
+    w = W.make(name)
+    print(f"[case {name} shape={w.image.shape}]", flush=True)
+    P = ora.params_of(w, threads=8)
+    ctx, img, lab = gpu_state(w)
+    lin_o, a_o, b_o = ora.particles(P, w.labels)
+    perm, lin, a, b = match_order(ctx, lin_o, b_o)
+    dl2 = S.compute_l2_diff(ctx)
+    o_l2 = ora.l2diff(P, w.image, w.labels, lin_o, a_o, b_o)
+    assert rel_err(dl2[: len(lin)].cpu().numpy()[perm], o_l2) <= REL_GRAD
+    dh1 = S.sobolev_smooth(ctx, dl2)[: len(lin)].cpu().numpy()[perm]
+    sel = np.random.default_rng(5).choice(len(lin_o), size=min(20000, len(lin_o)), replace=False)
+    o_h1 = ora.sobolev(P, lin_o, a_o, b_o, o_l2, sel=sel)
+    scale = np.abs(o_h1).max()
+    assert np.abs(dh1[sel] - o_h1).max() <= REL_GRAD * scale
+    L_next, info = ora.step(P, w.image, w.labels, ora.MODE_SOBOLEV)
+    S.step(ctx)
+    nd = compare_labels(S.get_labels(ctx).cpu().numpy(), L_next, info["lin"], info["dE_h1"])
+    print(f"  N={len(lin)} marginal label differences: {nd}")
