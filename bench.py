@@ -1,0 +1,146 @@
+#!/usr/bin/env python3
+"""Benchmark: contour-particle Sobolev updates per second on one MI355X.
+
+A step is one Region Competition iteration with Sobolev gradients -- the whole
+hot path: L2 gradient, cell-list Sobolev update, acceptance, statistics and
+particle-set update -- on the 3D 256^3 uint16 workload (25 ellipsoids, PC
+model, E = 6).  W warm-up iterations run first; the context is then
+re-initialised from the seeded labels (outside the timed region) and exactly K
+iterations are timed, so the timed region is the workload's first K
+iterations.  value = sum over timed iterations of the particle count N_t,
+divided by the wall time.
+
+Per-kernel durations come from HIP events recorded by the library on the
+launch stream inside the timed region; the dominant kernel's algorithmic bytes
+(per particle, times N_t) over its summed duration give the roofline figure.
+The CPU baseline times the FP64 oracle on a bounded sample of the same
+workload on the host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# Algorithmic bytes per particle for each kernel (each input read once, each
+# output written once; neighbour data reused on chip is not counted).
+#   k_l2diff : record 8 + intensity 2 (u16) + face-label stencil 3.4 + gradient write 4
+#   k_sobolev: record 8 + L2 gradient read 4 + Sobolev gradient write 4
+#   k_flip   : record 8 + gradient read 4
+#   k_write  : record write 8 (the particle set of the next iteration)
+ALG_BYTES = {"k_l2diff": 17.4, "k_sobolev": 16.0, "k_flip": 12.0, "k_write": 8.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=150)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ellipsoids3d_256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-events", action="store_true",
+                    help="time without per-kernel events (roofline omitted)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, budget_s):
+    """FP64 oracle iterations from the seeded start until the budget is spent."""
+    from oracle import oracle as O
+    threads = min(os.cpu_count() or 1, 16)
+    P = O.params_of(w, threads=threads)
+    L = w.labels.copy()
+    I = w.image.astype(np.float64)
+    done, upd = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < w.iterations:
+        L, info = O.step(P, I, L, O.MODE_SOBOLEV, want_arrays=False)
+        upd += info["n"]
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": upd / dt, "unit": "particle-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} iterations of {w.name} from the seeded start "
+                      f"({upd} particle updates in {dt:.1f} s, FP64, OpenMP over particles)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              f"(images are independent jobs: run one process per GPU)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1403_0240_amd import sobrc as S
+    from paper_1403_0240_amd import workloads as W
+
+    w = W.make(a.workload)
+    ctx, img, lab = S.from_workload(w)
+    S.init_labels(ctx, img, lab)
+    n0 = S.particle_count(ctx)
+    if a.warmup:
+        S.run(ctx, a.warmup, 0.0, S.MODE_SOBOLEV)
+    # timed region: the workload's first K iterations from the seeded labels
+    S.init_labels(ctx, img, lab)
+    use_events = not a.no_events
+    S.profile_enable(ctx, use_events)
+    S.profile_read(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = S.run(ctx, a.steps, 0.0, S.MODE_SOBOLEV)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = S.profile_read(ctx, reset=True) if use_events else None
+    hn, hf = S.get_history(ctx, cap=max(a.steps, 1))
+    assert done == a.steps == len(hn)
+    updates = int(hn.astype(np.int64).sum())
+
+    rec = {
+        "metric": "contour-particle Sobolev updates/s (frac. HBM roofline)",
+        "value": updates / dt,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "shape": list(w.image.shape),
+                   "image_dtype": str(w.image.dtype), "image_model": "piecewise-constant"
+                   if w.model == W.PC else "piecewise-smooth", "E": w.E, "lambda": w.lam,
+                   "particles_init": n0, "particles_mean": updates / a.steps,
+                   "flips_last": int(hf[-1]) if len(hf) else 0},
+    }
+    if prof:
+        kt = {k: {"ms_total": v[0], "launches": v[1],
+                  "us_avg": 1e3 * v[0] / v[1] if v[1] else 0.0} for k, v in prof.items()}
+        rec["kernels"] = kt
+        dom = max(kt, key=lambda k: kt[k]["ms_total"])
+        per = ALG_BYTES.get(dom)
+        if per is not None and kt[dom]["ms_total"] > 0:
+            achieved = per * updates / (kt[dom]["ms_total"] * 1e-3) / 1e9
+            rec["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": achieved,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                               "bytes_per_particle": per}
+        else:
+            rec["roofline"] = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None,
+                               "unit": None, "frac": None, "traffic": None}
+        rec["gradient_eval_us_per_iter"] = 1e3 * (kt["k_l2diff"]["ms_total"]
+                                                   + kt["k_sobolev"]["ms_total"]) / a.steps
+    if not a.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

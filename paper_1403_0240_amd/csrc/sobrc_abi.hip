@@ -40,14 +40,6 @@ int32_t dev_fail(hipError_t e, const char* where)
             return dev_fail(e_, where);        \
     } while (0)
 
-int log2_exact(int v)
-{
-    int s = 0;
-    while ((1 << s) < v)
-        ++s;
-    return s;
-}
-
 int32_t validate(const sobrc_params* p)
 {
     if (!p)
@@ -132,6 +124,31 @@ Geom make_geom(const sobrc_params* p)
     g.fx_scale = 1.0;
     g.fx_inv = 1.0;
     g.max_labels = p->max_labels;
+    g.small_m = p->max_labels <= kSmallM;
+    long long gp = (p->max_particles + kBlock - 1) / kBlock;
+    g.gp = (int)(gp < 1 ? 1 : (gp > kMaxGrid ? kMaxGrid : gp));
+    // emission ranges of Re = 2^lgRe tiles, at most kMaxGrid ranges unless a
+    // range would exceed kBlock tiles
+    g.lgRe = 0;
+    while ((1LL << g.lgRe) * kMaxGrid < g.ntiles && (1 << g.lgRe) < kBlock)
+        ++g.lgRe;
+    g.Re = 1 << g.lgRe;
+    g.ge = (g.ntiles + g.Re - 1) >> g.lgRe;
+    // Sobolev kernel: dense LDS brick for (ndim, h) when instantiated, else
+    // the generic staged scan
+    g.brick = g.h >= 1 && g.h <= (g.ndim == 3 ? kBrickMaxH3 : kBrickMaxH2);
+    g.full = g.T == (g.h + 1) * (g.h + 1);
+    int fixed = g.T * 4 + (kSobBlock / 64) * 4;
+    if (g.brick) {
+        int cap = (brick_lds_bytes(g.ndim, g.h) - fixed) / 12 / kSobBlock * kSobBlock;
+        g.stage_cap = cap > kStageCap ? kStageCap : cap;
+        g.sob_lds = 0;
+    } else {
+        g.stage_cap = kStageCap;
+        g.sob_lds = kStageCap * 12 + fixed;
+    }
+    int sg = g.ntiles < kMaxGrid ? g.ntiles : kMaxGrid;
+    g.sob_grid = (sg + 7) / 8 * 8;
     return g;
 }
 
@@ -148,7 +165,8 @@ void kernel_table(double E, double eps, int T, float* W)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t lab, rec0, rec1, ts0, ts1, act0, act1, tcnt, cand, dE, gH1, st_n, st_s1, flist, W, hist, ds;
+    size_t lab, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, dE, gH1, st_n, st_s1, lstat, W, hist,
+        part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, ds;
     size_t total;
 };
 
@@ -170,14 +188,21 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     L.act0 = take((size_t)g.ntiles * 4);
     L.act1 = take((size_t)g.ntiles * 4);
     L.tcnt = take((size_t)g.ntiles * 4);
-    L.cand = take((size_t)g.ntiles);
+    L.dirty = take((size_t)g.ntiles * 4);
     L.dE = take((size_t)cap * 4);
     L.gH1 = take((size_t)cap * 4);
     L.st_n = take((size_t)p->max_labels * 8);
     L.st_s1 = take((size_t)p->max_labels * 8);
-    L.flist = take((size_t)cap * 8);
+    L.lstat = take((size_t)p->max_labels * 16);
     L.W = take((size_t)kMaxT * 4);
     L.hist = take((size_t)2 * kHist * 4);
+    L.part_f = take((size_t)g.gp * 4);
+    L.part_n = take((size_t)g.gp * kSmallM * 8);
+    L.part_q = take((size_t)g.gp * kSmallM * 8);
+    L.part_cnt = take((size_t)g.ge * 4);
+    L.part_act = take((size_t)g.ge * 4);
+    L.part_off = take((size_t)g.ge * 4);
+    L.part_aoff = take((size_t)g.ge * 4);
     L.ds = take(sizeof(DevState));
     L.total = o;
     return L;
@@ -194,28 +219,41 @@ Bufs carve(const Layout& L, char* base, long long cap)
     b.active[0] = (unsigned*)(base + L.act0);
     b.active[1] = (unsigned*)(base + L.act1);
     b.tcnt = (unsigned*)(base + L.tcnt);
-    b.cand = (unsigned char*)(base + L.cand);
+    b.dirty = (unsigned*)(base + L.dirty);
     b.dE = (float*)(base + L.dE);
     b.gH1 = (float*)(base + L.gH1);
     b.st_n = (long long*)(base + L.st_n);
     b.st_s1 = (long long*)(base + L.st_s1);
-    b.flist = (uint2*)(base + L.flist);
+    b.lstat = (float4*)(base + L.lstat);
     b.W = (float*)(base + L.W);
     b.hist = (unsigned*)(base + L.hist);
+    b.part_f = (unsigned*)(base + L.part_f);
+    b.part_n = (long long*)(base + L.part_n);
+    b.part_q = (long long*)(base + L.part_q);
+    b.part_cnt = (unsigned*)(base + L.part_cnt);
+    b.part_act = (unsigned*)(base + L.part_act);
+    b.part_off = (unsigned*)(base + L.part_off);
+    b.part_aoff = (unsigned*)(base + L.part_aoff);
     b.ds = (DevState*)(base + L.ds);
     b.cap = (unsigned)cap;
     return b;
 }
 
-int grid_particles(long long cap)
+// Upload the kernel table W[d^2] (generic path) and fill the by-value weights
+// of the brick kernels.
+int32_t upload_tables(const Geom& g, double E, double eps, float* d_W, SobW* sw, hipStream_t s)
 {
-    long long g = (cap + kBlock - 1) / kBlock;
-    return (int)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
-}
-
-int grid_tiles(int ntiles)
-{
-    return ntiles < 2048 ? ntiles : 2048;
+    static thread_local float W[kMaxT];
+    memset(W, 0, sizeof W);
+    kernel_table(E, eps, g.T, W);
+    for (int k = 0; k < kMaxLim; ++k) {
+        sw->w[k] = k < g.T ? W[k] : 0.f;
+        sw->m[k] = k < g.T ? 1u : 0u;
+    }
+    SOBRC_HIP(hipMemcpyAsync(d_W, W, sizeof W, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    // the host array is reused by the next call: wait for the copy
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return SOBRC_OK;
 }
 
 }  // namespace
@@ -223,12 +261,16 @@ int grid_tiles(int ntiles)
 struct sobrc_ctx {
     sobrc_params p;
     Geom g;
+    SobW sw{};
     Layout L;
     Bufs b;
     const void* image = nullptr;
     int cur = 0;
     bool initialized = false;
-    int grid_p = 1, grid_t = 1;
+    // hipGraph of two consecutive steps, per start parity and mode
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2][2] = {};
+    float gtol[2][2] = {};
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev;   // pool, pairs
@@ -281,27 +323,81 @@ int32_t status_of(const DevState& h)
     return SOBRC_OK;
 }
 
+// Launch one iteration on stream s, reading state buffer `cur` and writing
+// the other; the host parity c->cur flips.
 int32_t launch_step(sobrc_ctx* c, int mode, int32_t* d_nflips, float tol, hipStream_t s)
 {
     int cur = c->cur, nxt = 1 - cur;
     const Geom& g = c->g;
     const Bufs& b = c->b;
     SOBRC_TRY(timed(c, SOBRC_K_L2DIFF, s, "k_l2diff",
-                    [&] { return launch_l2diff(g, b, c->image, cur, b.dE, 1, c->grid_p, s); }));
+                    [&] { return launch_l2diff(g, b, c->image, cur, b.dE, 1, s); }));
     const float* grad = b.dE;
     if (mode == SOBRC_MODE_SOBOLEV) {
         SOBRC_TRY(timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
-                        [&] { return launch_sobolev(g, b, cur, b.dE, b.gH1, 1, c->grid_t, s); }));
+                        [&] { return launch_sobolev(g, b, c->sw, cur, b.dE, b.gH1, 1, s); }));
         grad = b.gH1;
     }
-    SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip",
-                    [&] { return launch_flip(g, b, c->image, cur, grad, c->grid_p, s); }));
-    SOBRC_TRY(timed(c, SOBRC_K_COUNT, s, "k_count", [&] { return launch_count(g, b, c->grid_t, 1, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip", [&] { return launch_flip(g, b, c->image, cur, grad, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_COUNT, s, "k_count", [&] { return launch_count(g, b, cur, 1, 0, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_SCAN, s, "k_scan",
                     [&] { return launch_scan(g, b, cur, nxt, 0, tol, d_nflips, 1, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_WRITE, s, "k_write",
-                    [&] { return launch_write(g, b, c->image, cur, nxt, c->grid_t, s); }));
+                    [&] { return launch_write(g, b, c->image, cur, nxt, grad, 0, s); }));
     c->cur = nxt;
+    return SOBRC_OK;
+}
+
+void drop_graphs(sobrc_ctx* c)
+{
+    for (auto& row : c->gexec)
+        for (auto& e : row)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+}
+
+// Instantiate (once per start parity, mode and tolerance) a graph holding two
+// consecutive iterations; run() replays it.  Captured on a private stream.
+int32_t pair_graph(sobrc_ctx* c, int mode, float tol, hipGraphExec_t* out)
+{
+    int par = c->cur;
+    hipGraphExec_t& e = c->gexec[par][mode];
+    if (e && c->gtol[par][mode] == tol) {
+        *out = e;
+        return SOBRC_OK;
+    }
+    if (e) {
+        (void)hipGraphExecDestroy(e);
+        e = nullptr;
+    }
+    if (!c->cap_stream)
+        SOBRC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    bool prof = c->prof;
+    c->prof = false;
+    hipGraph_t graph = nullptr;
+    SOBRC_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    int32_t r1 = launch_step(c, mode, nullptr, tol, c->cap_stream);
+    int32_t r2 = r1 == SOBRC_OK ? launch_step(c, mode, nullptr, tol, c->cap_stream) : r1;
+    hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+    c->prof = prof;
+    c->cur = par;  // capture only recorded the launches
+    if (r2 != SOBRC_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return r2;
+    }
+    if (ec != hipSuccess)
+        return dev_fail(ec, "hipStreamEndCapture");
+    hipError_t ei = hipGraphInstantiate(&e, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        e = nullptr;
+        return dev_fail(ei, "hipGraphInstantiate");
+    }
+    c->gtol[par][mode] = tol;
+    *out = e;
     return SOBRC_OK;
 }
 
@@ -344,8 +440,6 @@ int32_t ctx_create(const sobrc_params* params, void* d_workspace, size_t bytes, 
     c->g = g;
     c->L = L;
     c->b = carve(L, (char*)d_workspace, params->max_particles);
-    c->grid_p = grid_particles(params->max_particles);
-    c->grid_t = grid_tiles(g.ntiles);
     *out = c;
     return SOBRC_OK;
 }
@@ -356,6 +450,9 @@ int32_t ctx_destroy(sobrc_ctx* ctx)
         return fail(SOBRC_EINVAL, "ctx is NULL");
     for (hipEvent_t e : ctx->ev)
         (void)hipEventDestroy(e);
+    drop_graphs(ctx);
+    if (ctx->cap_stream)
+        (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return SOBRC_OK;
 }
@@ -368,17 +465,18 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
         return fail(SOBRC_EINVAL, "image and labels must be device pointers");
     hipStream_t s = (hipStream_t)stream;
     c->initialized = false;
+    drop_graphs(c);  // graphs hold the image pointer and the intensity scale
     c->image = d_image;
     Geom& g = c->g;
     const Bufs& b = c->b;
-    // state block, statistics and candidate flags start cleared
+    // state block and statistics start cleared; every tile is scanned once
     SOBRC_HIP(hipMemsetAsync(b.ds, 0, sizeof(DevState), s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.st_n, 0, (size_t)c->p.max_labels * 8, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.st_s1, 0, (size_t)c->p.max_labels * 8, s), "hipMemsetAsync");
-    SOBRC_HIP(hipMemsetAsync(b.cand, 1, (size_t)g.ntiles, s), "hipMemsetAsync");
-    std::vector<float> W(kMaxT, 0.f);
-    kernel_table(c->p.E, c->p.eps, g.T, W.data());
-    SOBRC_HIP(hipMemcpyAsync(b.W, W.data(), sizeof(float) * kMaxT, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipMemsetAsync(b.dirty, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(b.part_cnt, 0, (size_t)g.ge * 4, s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(b.part_act, 0, (size_t)g.ge * 4, s), "hipMemsetAsync");
+    SOBRC_TRY(upload_tables(g, c->p.E, c->p.eps, b.W, &c->sw, s));
     SOBRC_HIP(launch_init_labels(g, b, d_labels, d_image, s), "k_init_labels");
     DevState h;
     SOBRC_TRY(read_state(c, &h, s));
@@ -401,9 +499,9 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
         g.fx_inv = ldexp(1.0, -s2);
     }
     SOBRC_HIP(launch_stats_init(g, b, d_image, s), "k_stats_init");
-    SOBRC_HIP(launch_count(g, b, c->grid_t, 0, s), "k_count");
+    SOBRC_HIP(launch_count(g, b, 0, 0, 1, s), "k_count");
     SOBRC_HIP(launch_scan(g, b, 0, 0, 1, 0.f, nullptr, 0, s), "k_scan");
-    SOBRC_HIP(launch_write(g, b, d_image, 0, 0, c->grid_t, s), "k_write");
+    SOBRC_HIP(launch_write(g, b, d_image, 0, 0, nullptr, 1, s), "k_write");
     SOBRC_TRY(read_state(c, &h, s));
     if (h.err & kErrCapacity)
         return fail(SOBRC_ECAPACITY, "initial particle set needs %u entries > max_particles %lld", h.need,
@@ -423,7 +521,7 @@ int32_t compute_l2_diff(sobrc_ctx* c, float* d_dE_l2, void* stream)
         return fail(SOBRC_EINVAL, "output is NULL");
     hipStream_t s = (hipStream_t)stream;
     return timed(c, SOBRC_K_L2DIFF, s, "k_l2diff",
-                 [&] { return launch_l2diff(c->g, c->b, c->image, c->cur, d_dE_l2, 0, c->grid_p, s); });
+                 [&] { return launch_l2diff(c->g, c->b, c->image, c->cur, d_dE_l2, 0, s); });
 }
 
 int32_t sobolev_smooth(sobrc_ctx* c, const float* d_in, float* d_out, void* stream)
@@ -438,7 +536,7 @@ int32_t sobolev_smooth(sobrc_ctx* c, const float* d_in, float* d_out, void* stre
         return fail(SOBRC_EINVAL, "input and output must be distinct buffers (Jacobi update)");
     hipStream_t s = (hipStream_t)stream;
     return timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
-                 [&] { return launch_sobolev(c->g, c->b, c->cur, d_in, d_out, 0, c->grid_t, s); });
+                 [&] { return launch_sobolev(c->g, c->b, c->sw, c->cur, d_in, d_out, 0, s); });
 }
 
 int32_t step(sobrc_ctx* c, int32_t mode, int32_t* d_nflips, void* stream)
@@ -469,7 +567,14 @@ int32_t run(sobrc_ctx* c, int32_t max_iters, double flip_tol, int32_t mode, int3
     unsigned it0 = h.iters;
     // a previous run may have stopped on its tolerance: start afresh
     SOBRC_HIP(hipMemsetAsync(&c->b.ds->converged, 0, sizeof(unsigned), s), "hipMemsetAsync");
-    for (int t = 0; t < max_iters; ++t)
+    int t = 0;
+    if (!c->prof && max_iters >= 2) {
+        hipGraphExec_t e = nullptr;
+        SOBRC_TRY(pair_graph(c, mode, (float)flip_tol, &e));
+        for (; t + 2 <= max_iters; t += 2)
+            SOBRC_HIP(hipGraphLaunch(e, s), "hipGraphLaunch");
+    }
+    for (; t < max_iters; ++t)
         SOBRC_TRY(launch_step(c, mode, nullptr, (float)flip_tol, s));
     SOBRC_TRY(read_state(c, &h, s));
     if (h_iters_done)
@@ -639,9 +744,8 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const in
     unsigned* fill = (unsigned*)(base + L.fill);
     unsigned* origin = (unsigned*)(base + L.origin);
     hipStream_t s = (hipStream_t)stream;
-    std::vector<float> W(kMaxT, 0.f);
-    kernel_table(params->E, params->eps, g.T, W.data());
-    SOBRC_HIP(hipMemcpyAsync(b.W, W.data(), sizeof(float) * kMaxT, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    SobW sw{};
+    SOBRC_TRY(upload_tables(g, params->E, params->eps, b.W, &sw, s));
     SOBRC_HIP(hipMemsetAsync(b.ds, 0, sizeof(DevState), s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.tcnt, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(fill, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
@@ -651,9 +755,9 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const in
     SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (h.err & kErrInput)
         return fail(SOBRC_EINVAL, "particle outside the image or with a bad label pair");
-    SOBRC_HIP(launch_scan(g, b, 0, 0, 1, 0.f, nullptr, 0, s), "k_scan");
+    SOBRC_HIP(launch_bin_scan(g, b, s), "k_bin_scan");
     SOBRC_HIP(launch_bin_scatter(g, b, n, d_lin, d_a, d_b, d_in, fill, origin, s), "k_bin_scatter");
-    SOBRC_HIP(launch_sobolev(g, b, 0, b.dE, b.gH1, 0, grid_tiles(g.ntiles), s), "k_sobolev");
+    SOBRC_HIP(launch_sobolev(g, b, sw, 0, b.dE, b.gH1, 0, s), "k_sobolev");
     SOBRC_HIP(launch_unbin(b, n, origin, b.gH1, d_out, s), "k_unbin");
     return SOBRC_OK;
 }

@@ -6,10 +6,39 @@
 namespace sobrc {
 
 constexpr int kBlock = 256;        // threads per block of the particle/tile kernels
-constexpr int kScanThreads = 1024; // single-block tile scan
+constexpr int kSobBlock = 256;     // threads per block of the Sobolev kernels
+constexpr int kScanThreads = 1024; // single-block scan of per-block partials
 constexpr int kHist = 4096;        // telemetry ring (iterations)
-constexpr int kStageCap = 2048;    // staged neighbour particles per round (k_sobolev)
+constexpr int kStageCap = 2048;    // staged neighbour particles per round (generic Sobolev path)
 constexpr int kMaxT = 1024;        // support table entries: d^2 < T <= (E/2)^2 rounded up
+constexpr int kMaxLim = 81;        // (h+1)^2 for the largest brick halo (2D, h = 8)
+constexpr int kSmallM = 16;        // label counts up to this use per-block statistics partials
+constexpr int kMaxGrid = 2048;     // blocks of the particle and emission kernels
+
+// Largest axis offset h with h*h < T: the halo a Sobolev brick needs.
+// Bricks exist for 3D halos 1..4 (8^3 tiles) and 2D halos 1..8 (16^2 tiles).
+constexpr int kBrickMaxH3 = 4;
+constexpr int kBrickMaxH2 = 8;
+
+// LDS bytes of a brick kernel: the dense brick (two fp32 values and one packed
+// count word per cell) or, if larger, the generic path's staging of 256
+// particles with its weight table.
+__host__ __device__ constexpr int brick_cells(int nd, int h)
+{
+    return nd == 3 ? (8 + 2 * h) * (8 + 2 * h) * (8 + 2 * h) : (16 + 2 * h) * (16 + 2 * h);
+}
+__host__ __device__ constexpr int brick_lds_bytes(int nd, int h)
+{
+    return brick_cells(nd, h) * 12 > 256 * 12 + kMaxLim * 4 + 16 ? brick_cells(nd, h) * 12
+                                                                   : 256 * 12 + kMaxLim * 4 + 16;
+}
+
+// Kernel weights by integer squared distance: w[d2] = K(sqrt(d2)) inside the
+// support (d2 < T), 0 outside; m[d2] = 1 inside, 0 outside.
+struct SobW {
+    float w[kMaxLim];
+    unsigned m[kMaxLim];
+};
 
 // error bits kept on the device (sticky until init_labels)
 constexpr unsigned kErrCapacity = 1u;
@@ -32,6 +61,14 @@ struct Geom {
     double fx_scale;            // fixed-point scale of intensity sums (2^s)
     double fx_inv;              // 1 / fx_scale
     int max_labels;
+    int small_m;                // max_labels <= kSmallM
+    int gp;                     // blocks of the particle kernels (l2diff, flip)
+    int ge, Re, lgRe;           // emission ranges: count, tiles per range (2^lgRe)
+    int brick;                  // Sobolev brick kernel for (ndim, h) exists
+    int full;                   // T == (h+1)^2: every offset of the brick stencil is inside
+    int stage_cap;              // generic-path staging capacity
+    int sob_lds;                // dynamic LDS bytes of the generic Sobolev kernel
+    int sob_grid;               // blocks of the Sobolev kernels (multiple of 8)
 };
 
 // Device-resident control block of a context.
@@ -39,7 +76,7 @@ struct DevState {
     unsigned n[2];          // particle count of state buffer 0/1
     unsigned n_active[2];   // non-empty tiles of state buffer 0/1
     unsigned nflips;        // pixels changed by the running step
-    unsigned nflip_list;    // entries in the flip list of the running step
+    unsigned epoch;         // iteration stamp of dirty tiles (bumped at each step start)
     unsigned err;           // sticky error bits
     unsigned undo;          // running step overflowed: roll back in k_write
     unsigned go;            // running step passed k_scan and commits in k_write
@@ -57,14 +94,21 @@ struct Bufs {
     unsigned* tstart[2];     // tile_start, ntiles + 1 each
     unsigned* active[2];     // non-empty tiles, ntiles each
     unsigned* tcnt;          // per-tile particle count of the next state
-    unsigned char* cand;     // tiles to scan for particles in the next emission
+    unsigned* dirty;         // epoch of the last flip within one pixel of the tile
     float* dE;               // L2 gradient, capacity
     float* gH1;              // Sobolev gradient, capacity
     long long* st_n;         // region pixel counts, max_labels
     long long* st_s1;        // region intensity sums (fixed point), max_labels
-    uint2* flist;            // flips of the running step {lin, a | b << 16}
+    float4* lstat;           // per label: mean, n/(n-1) (0 if n <= 1), n/(n+1)
     float* W;                // kernel table W[d^2], T entries
     unsigned* hist;          // 2 * kHist: N_t and flips_t
+    unsigned* part_f;        // flips per k_flip block
+    long long* part_n;       // per label x k_flip block: pixel-count deltas (small M)
+    long long* part_q;       // per label x k_flip block: intensity-sum deltas (small M)
+    unsigned* part_cnt;      // particles per emission block (tiles [b*Re, (b+1)*Re))
+    unsigned* part_act;      // non-empty tiles per emission block
+    unsigned* part_off;      // exclusive prefix of part_cnt
+    unsigned* part_aoff;     // exclusive prefix of part_act
     DevState* ds;
     unsigned cap;
 };
@@ -74,16 +118,16 @@ hipError_t launch_init_labels(const Geom& g, const Bufs& b, const int32_t* label
                               const void* img, hipStream_t s);
 hipError_t launch_stats_init(const Geom& g, const Bufs& b, const void* img, hipStream_t s);
 hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur, float* out,
-                         int gated, int grid, hipStream_t s);
-hipError_t launch_sobolev(const Geom& g, const Bufs& b, int cur, const float* in, float* out,
-                          int gated, int grid, hipStream_t s);
+                         int gated, hipStream_t s);
+hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* in,
+                          float* out, int gated, hipStream_t s);
 hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,
-                       int grid, hipStream_t s);
-hipError_t launch_count(const Geom& g, const Bufs& b, int grid, int gated, hipStream_t s);
+                       hipStream_t s);
+hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, hipStream_t s);
 hipError_t launch_scan(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol,
                        int32_t* d_nflips, int gated, hipStream_t s);
-hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, int nxt, int grid,
-                        hipStream_t s);
+hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, int nxt,
+                        const float* grad, int all_dirty, hipStream_t s);
 hipError_t launch_unpack(const Geom& g, const Bufs& b, int cur, int32_t* lin, int32_t* a,
                          int32_t* bb, hipStream_t s);
 hipError_t launch_labels_out(const Geom& g, const Bufs& b, int32_t* out, hipStream_t s);
@@ -91,6 +135,7 @@ hipError_t launch_labels_out(const Geom& g, const Bufs& b, int32_t* out, hipStre
 // Stateless binning for sobolev_smooth_particles.
 hipError_t launch_bin_count(const Geom& g, const Bufs& b, long long n, const int32_t* lin,
                             const int32_t* a, const int32_t* bb, hipStream_t s);
+hipError_t launch_bin_scan(const Geom& g, const Bufs& b, hipStream_t s);
 hipError_t launch_bin_scatter(const Geom& g, const Bufs& b, long long n, const int32_t* lin,
                               const int32_t* a, const int32_t* bb, const float* in,
                               unsigned* fill, unsigned* origin, hipStream_t s);
