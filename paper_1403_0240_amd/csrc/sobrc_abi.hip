@@ -134,20 +134,38 @@ Geom make_geom(const sobrc_params* p)
         ++g.lgRe;
     g.Re = 1 << g.lgRe;
     g.ge = (g.ntiles + g.Re - 1) >> g.lgRe;
+    // a multiplier near ntiles * (golden ratio - 1) that is coprime with ntiles
+    {
+        unsigned long long c = (unsigned long long)((double)g.ntiles * 0.6180339887) | 1ull;
+        auto gcd = [](unsigned long long x, unsigned long long y) {
+            while (y) {
+                unsigned long long r = x % y;
+                x = y;
+                y = r;
+            }
+            return x;
+        };
+        while (g.ntiles > 1 && gcd(c, (unsigned long long)g.ntiles) != 1)
+            c += 2;
+        g.deal = (unsigned)(g.ntiles > 1 ? c % (unsigned long long)g.ntiles : 0);
+        if (g.ntiles > 1 && g.deal == 0)
+            g.deal = 1;
+    }
     // Sobolev kernel: dense LDS brick for (ndim, h) when instantiated, else
     // the generic staged scan
     g.brick = g.h >= 1 && g.h <= (g.ndim == 3 ? kBrickMaxH3 : kBrickMaxH2);
     g.full = g.T == (g.h + 1) * (g.h + 1);
     int fixed = g.T * 4 + (kSobBlock / 64) * 4;
+    // The brick kernel falls back to the staged scan inside its static LDS,
+    // so the staging capacity must fit there; the generic kernel (also used
+    // by the stateless entry point) takes the same capacity as dynamic LDS.
+    g.stage_cap = kStageCap;
     if (g.brick) {
         int cap = (brick_lds_bytes(g.ndim, g.h) - fixed) / 12 / kSobBlock * kSobBlock;
         g.stage_cap = cap > kStageCap ? kStageCap : cap;
-        g.sob_lds = 0;
-    } else {
-        g.stage_cap = kStageCap;
-        g.sob_lds = kStageCap * 12 + fixed;
     }
-    int sg = g.ntiles < kMaxGrid ? g.ntiles : kMaxGrid;
+    g.sob_lds = g.stage_cap * 12 + fixed;
+    int sg = g.ntiles < 2 * kMaxGrid ? g.ntiles : 2 * kMaxGrid;  // mostly one tile per block
     g.sob_grid = (sg + 7) / 8 * 8;
     return g;
 }
@@ -165,7 +183,7 @@ void kernel_table(double E, double eps, int T, float* W)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t lab, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, dE, gH1, st_n, st_s1, lstat, W, hist,
+    size_t lab, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
         part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, ds;
     size_t total;
 };
@@ -189,6 +207,7 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     L.act1 = take((size_t)g.ntiles * 4);
     L.tcnt = take((size_t)g.ntiles * 4);
     L.dirty = take((size_t)g.ntiles * 4);
+    L.tslot = take((size_t)g.ntiles * kSlotWords * 4);
     L.dE = take((size_t)cap * 4);
     L.gH1 = take((size_t)cap * 4);
     L.st_n = take((size_t)p->max_labels * 8);
@@ -220,6 +239,7 @@ Bufs carve(const Layout& L, char* base, long long cap)
     b.active[1] = (unsigned*)(base + L.act1);
     b.tcnt = (unsigned*)(base + L.tcnt);
     b.dirty = (unsigned*)(base + L.dirty);
+    b.tslot = (unsigned*)(base + L.tslot);
     b.dE = (float*)(base + L.dE);
     b.gH1 = (float*)(base + L.gH1);
     b.st_n = (long long*)(base + L.st_n);
@@ -335,7 +355,7 @@ int32_t launch_step(sobrc_ctx* c, int mode, int32_t* d_nflips, float tol, hipStr
     const float* grad = b.dE;
     if (mode == SOBRC_MODE_SOBOLEV) {
         SOBRC_TRY(timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
-                        [&] { return launch_sobolev(g, b, c->sw, cur, b.dE, b.gH1, 1, s); }));
+                        [&] { return launch_sobolev(g, b, c->sw, cur, b.dE, b.gH1, 1, 1, s); }));
         grad = b.gH1;
     }
     SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip", [&] { return launch_flip(g, b, c->image, cur, grad, s); }));
@@ -536,7 +556,7 @@ int32_t sobolev_smooth(sobrc_ctx* c, const float* d_in, float* d_out, void* stre
         return fail(SOBRC_EINVAL, "input and output must be distinct buffers (Jacobi update)");
     hipStream_t s = (hipStream_t)stream;
     return timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
-                 [&] { return launch_sobolev(c->g, c->b, c->sw, c->cur, d_in, d_out, 0, s); });
+                 [&] { return launch_sobolev(c->g, c->b, c->sw, c->cur, d_in, d_out, 0, 1, s); });
 }
 
 int32_t step(sobrc_ctx* c, int32_t mode, int32_t* d_nflips, void* stream)
@@ -757,7 +777,7 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const in
         return fail(SOBRC_EINVAL, "particle outside the image or with a bad label pair");
     SOBRC_HIP(launch_bin_scan(g, b, s), "k_bin_scan");
     SOBRC_HIP(launch_bin_scatter(g, b, n, d_lin, d_a, d_b, d_in, fill, origin, s), "k_bin_scatter");
-    SOBRC_HIP(launch_sobolev(g, b, sw, 0, b.dE, b.gH1, 0, s), "k_sobolev");
+    SOBRC_HIP(launch_sobolev(g, b, sw, 0, b.dE, b.gH1, 0, 0, s), "k_sobolev");
     SOBRC_HIP(launch_unbin(b, n, origin, b.gH1, d_out, s), "k_unbin");
     return SOBRC_OK;
 }

@@ -17,6 +17,13 @@ constexpr int kMaxGrid = 2048;     // blocks of the particle and emission kernel
 
 // Largest axis offset h with h*h < T: the halo a Sobolev brick needs.
 // Bricks exist for 3D halos 1..4 (8^3 tiles) and 2D halos 1..8 (16^2 tiles).
+// Emission slot of a tile (written by the particle count when the tile is
+// dirty, valid until it is dirty again): word 0 = lo | hi << 16 of a
+// two-label box (0xFFFF: several labels); words 1..64: per tile row
+// (ly + TY*lz), particle bits | bits of pixels labelled lo << 16; words
+// 65..128: particles in the rows before (the row's offset in the tile).
+constexpr int kSlotRows = 64;
+constexpr int kSlotWords = 1 + 2 * kSlotRows;
 constexpr int kBrickMaxH3 = 4;
 constexpr int kBrickMaxH2 = 8;
 
@@ -64,6 +71,7 @@ struct Geom {
     int small_m;                // max_labels <= kSmallM
     int gp;                     // blocks of the particle kernels (l2diff, flip)
     int ge, Re, lgRe;           // emission ranges: count, tiles per range (2^lgRe)
+    unsigned deal;              // multiplier coprime with ntiles dealing dirty tiles to blocks
     int brick;                  // Sobolev brick kernel for (ndim, h) exists
     int full;                   // T == (h+1)^2: every offset of the brick stencil is inside
     int stage_cap;              // generic-path staging capacity
@@ -95,6 +103,7 @@ struct Bufs {
     unsigned* active[2];     // non-empty tiles, ntiles each
     unsigned* tcnt;          // per-tile particle count of the next state
     unsigned* dirty;         // epoch of the last flip within one pixel of the tile
+    unsigned* tslot;         // per tile: emission bitmasks from k_count for k_write
     float* dE;               // L2 gradient, capacity
     float* gH1;              // Sobolev gradient, capacity
     long long* st_n;         // region pixel counts, max_labels
@@ -120,7 +129,7 @@ hipError_t launch_stats_init(const Geom& g, const Bufs& b, const void* img, hipS
 hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur, float* out,
                          int gated, hipStream_t s);
 hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* in,
-                          float* out, int gated, hipStream_t s);
+                          float* out, int gated, int use_slots, hipStream_t s);
 hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,
                        hipStream_t s);
 hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, hipStream_t s);

@@ -304,112 +304,190 @@ __device__ __forceinline__ unsigned block_reduce_u(unsigned v, unsigned* s_red, 
     return r;
 }
 
-struct EmitLds {
-    unsigned short box[kBoxMax];
-    unsigned red[kBlock / 64];
+// Per-wave LDS of one tile's emission: the label box and per-row label masks.
+struct WaveEmit {
+    unsigned short box[kBoxMax / 2];
     unsigned mlo[128], mhi[128];
-    unsigned total;
 };
 
-// Particles of tile t under the current labels.  Counts them (WRITE = false)
-// or writes their records in canonical order starting at rec[o] (WRITE = true).
-// A box (tile + one-pixel halo) holding only two labels lo < hi takes the bit
-// path: per box row, masks of "label == lo" and "label == hi"; a pixel is a
-// particle iff its 3x3(x3) neighbourhood holds both labels, i.e. iff the OR of
-// both dilated masks over the neighbourhood is set in both.  Other boxes
-// enumerate the distinct neighbour labels of every pixel.
-template <bool WRITE>
-__device__ unsigned emit_tile(const Geom& g, const unsigned short* __restrict__ lab, unsigned t, EmitLds& L,
-                              uint2* rec, unsigned o)
+// Order LDS writes of this wave before its later reads (a wave's LDS
+// operations complete in order; this keeps the compiler from reordering).
+__device__ __forceinline__ void wave_lds_sync()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ unsigned wave_excl_scan_u(unsigned v, unsigned& total)
+{
+    const int lane = lane_id();
+    unsigned inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        unsigned u = __shfl_up(inc, d);
+        if (lane >= d)
+            inc += u;
+    }
+    total = __shfl(inc, 63);
+    return inc - v;
+}
+
+// Label box of a tile (tile + one-pixel halo) into LDS by one wave: all of a
+// lane's loads are issued before any is stored, so their latencies overlap.
+__device__ void wave_load_box(const Geom& g, const unsigned short* __restrict__ lab, unsigned short* box,
+                              const TileInfo& ti)
+{
+    constexpr int kPer = kBoxMax / 2 / 64;  // box entries per lane (box <= 1024)
+    const int nbox = ti.BX * ti.BY * ti.BZ;
+    const int ox = ti.tx * ti.TX - 1, oy = ti.ty * ti.TY - 1, oz = ti.tz * ti.TZ - ti.hz;
+    const int lane = lane_id();
+    // walk the box in (x, y, z) steps of 64 cells without divisions per entry
+    int bx = lane % ti.BX, by = (lane / ti.BX) % ti.BY, bz = lane / (ti.BX * ti.BY);
+    const int sx = 64 % ti.BX, sy = (64 / ti.BX) % ti.BY, sz = 64 / (ti.BX * ti.BY);
+    unsigned short v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int k = lane + 64 * u;
+        int x = ox + bx, y = oy + by, z = oz + bz;
+        bool in = k < nbox && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+        v[u] = in ? lab[lin_of(g, x, y, z)] : kNone;
+        bx += sx;
+        int cy = bx >= ti.BX;
+        bx -= cy ? ti.BX : 0;
+        by += sy + cy;
+        int cz = by >= ti.BY;
+        by -= cz ? ti.BY : 0;
+        bz += sz + cz;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int k = lane + 64 * u;
+        if (k < nbox)
+            box[k] = v[u];
+    }
+    wave_lds_sync();
+}
+
+// Particles of tile t under the current labels, counted by one wave.  A box
+// (tile + one-pixel halo) holding two labels lo < hi takes the bit path: per
+// box row, masks of "label == lo" and "label == hi"; a pixel is a particle iff
+// its 3x3(x3) neighbourhood holds both labels, i.e. iff the OR of the dilated
+// masks over the neighbourhood is set in both.  The tile's slot keeps, per
+// tile row, the particle bits and the bits of pixels labelled lo, so the
+// records can be written later without the labels; other boxes are marked
+// for a full re-enumeration (slot word 0 = 0xFFFF).
+__device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restrict__ lab, unsigned t,
+                                    WaveEmit& W, unsigned* __restrict__ slot)
+{
+    const int lane = lane_id();
     TileInfo ti = tile_info(g, t);
-    __syncthreads();
-    load_label_box(g, lab, L.box, ti);
-    __syncthreads();
+    wave_load_box(g, lab, W.box, ti);
     const int nbox = ti.BX * ti.BY * ti.BZ;
     unsigned mn = 0xffffu, mx = 0u;
-    for (int k = threadIdx.x; k < nbox; k += kBlock) {
-        unsigned l = L.box[k];
+    for (int k = lane; k < nbox; k += 64) {
+        unsigned l = W.box[k];
         if (l != kNone) {
             mn = l < mn ? l : mn;
             mx = l > mx ? l : mx;
         }
     }
-    mn = block_reduce_u(mn, L.red, 0);
-    mx = block_reduce_u(mx, L.red, 1);
-    if (mx <= mn)
-        return 0;  // one label (or none): no contour in this tile
-    unsigned third = 0;
-    for (int k = threadIdx.x; k < nbox; k += kBlock) {
-        unsigned l = L.box[k];
-        third |= (l != kNone && l != mn && l != mx) ? 1u : 0u;
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned a = __shfl_xor(mn, o), c = __shfl_xor(mx, o);
+        mn = a < mn ? a : mn;
+        mx = c > mx ? c : mx;
     }
-    third = block_reduce_u(third, L.red, 2);
+    if (mx <= mn)
+        return 0;  // one label: no contour in this tile
+    bool third = false;
+    for (int k = lane; k < nbox; k += 64) {
+        unsigned l = W.box[k];
+        third = third || (l != kNone && l != mn && l != mx);
+    }
     const int BXY = ti.BX * ti.BY, zr = ti.hz;
-    if (!third) {
-        const int nrow = ti.BY * ti.BZ;
-        for (int r = threadIdx.x; r < nrow; r += kBlock) {
-            unsigned ml = 0, mh = 0;
-            for (int bx = 0; bx < ti.BX; ++bx) {
-                unsigned l = L.box[r * ti.BX + bx];
-                ml |= (l == mn ? 1u : 0u) << bx;
-                mh |= (l == mx ? 1u : 0u) << bx;
-            }
-            L.mlo[r] = ml;
-            L.mhi[r] = mh;
+    if (__ballot(third) != 0) {
+        const int nv = ti.TX * ti.TY * ti.TZ;
+        unsigned cc = 0;
+        for (int v = lane; v < nv; v += 64) {
+            int lx = v & (ti.TX - 1), ly = (v >> g.tsx) & (ti.TY - 1), lz = v >> (g.tsx + g.tsy);
+            int x = ti.tx * ti.TX + lx, y = ti.ty * ti.TY + ly, z = ti.tz * ti.TZ + lz;
+            if (x >= g.nx || y >= g.ny || z >= g.nz)
+                continue;
+            int cidx = (lx + 1) + ti.BX * ((ly + 1) + ti.BY * (lz + ti.hz));
+            int lo, hi;
+            cc += neighbour_span(W.box, cidx, ti.BX, BXY, zr, W.box[cidx], lo, hi);
         }
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            const int nr = ti.TY * ti.TZ;  // interior rows, at most 64
-            const int lane = threadIdx.x;
-            unsigned pb = 0, own_lo = 0;
-            int ly = 0, lz = 0;
-            if (lane < nr) {
-                ly = lane & (ti.TY - 1);
-                lz = lane >> g.tsy;
-                int by = ly + 1, bz = lz + ti.hz;
-                unsigned ol = 0, oh = 0;
-                for (int dz = -zr; dz <= zr; ++dz)
-                    for (int dy = -1; dy <= 1; ++dy) {
-                        int r = (by + dy) + ti.BY * (bz + dz);
-                        unsigned ml = L.mlo[r], mh = L.mhi[r];
-                        ol |= ml | (ml << 1) | (ml >> 1);
-                        oh |= mh | (mh << 1) | (mh >> 1);
-                    }
-                int rc = by + ti.BY * bz;
-                unsigned cl = L.mlo[rc], ch = L.mhi[rc];
-                pb = ((ol & oh & (cl | ch)) >> 1) & ((1u << ti.TX) - 1u);
-                own_lo = cl >> 1;
-            }
-            unsigned cnt = (unsigned)__popc(pb);
-            if (WRITE) {
-                unsigned inc = cnt;
-                for (int d = 1; d < 64; d <<= 1) {
-                    unsigned u = __shfl_up(inc, d);
-                    if (lane >= d)
-                        inc += u;
-                }
-                unsigned oo = o + inc - cnt;
-                int y = ti.ty * ti.TY + ly, z = ti.tz * ti.TZ + lz;
-                while (pb) {
-                    int lx = __ffs(pb) - 1;
-                    pb &= pb - 1;
-                    bool isl = (own_lo >> lx) & 1u;
-                    unsigned own = isl ? mn : mx, oth = isl ? mx : mn;
-                    rec[oo++] = make_uint2(pack(g, ti.tx * ti.TX + lx, y, z), own | (oth << 16));
-                }
-            }
-            cnt = wave_sum_u(cnt);
-            if (lane == 0)
-                L.total = cnt;
+        if (lane == 0)
+            slot[0] = 0xffffu;
+        return wave_sum_u(cc);
+    }
+    const int nrow = ti.BY * ti.BZ;
+    for (int r = lane; r < nrow; r += 64) {
+        unsigned ml = 0, mh = 0;
+        for (int bx = 0; bx < ti.BX; ++bx) {
+            unsigned l = W.box[r * ti.BX + bx];
+            ml |= (l == mn ? 1u : 0u) << bx;
+            mh |= (l == mx ? 1u : 0u) << bx;
         }
-        __syncthreads();
-        return L.total;
+        W.mlo[r] = ml;
+        W.mhi[r] = mh;
+    }
+    wave_lds_sync();
+    unsigned pb = 0;
+    if (lane < ti.TY * ti.TZ) {  // one interior row per lane (at most 64)
+        int by = (lane & (ti.TY - 1)) + 1, bz = (lane >> g.tsy) + ti.hz;
+        unsigned ol = 0, oh = 0;
+        for (int dz = -zr; dz <= zr; ++dz)
+            for (int dy = -1; dy <= 1; ++dy) {
+                int r = (by + dy) + ti.BY * (bz + dz);
+                unsigned ml = W.mlo[r], mh = W.mhi[r];
+                ol |= ml | (ml << 1) | (ml >> 1);
+                oh |= mh | (mh << 1) | (mh >> 1);
+            }
+        int rc = by + ti.BY * bz;
+        unsigned cl = W.mlo[rc], ch = W.mhi[rc];
+        unsigned tmask = (1u << ti.TX) - 1u;
+        pb = ((ol & oh & (cl | ch)) >> 1) & tmask;
+        slot[1 + lane] = pb | (((cl >> 1) & tmask) << 16);
+    }
+    unsigned tot;
+    const unsigned pre = wave_excl_scan_u((unsigned)__popc(pb), tot);
+    if (lane < ti.TY * ti.TZ)
+        slot[1 + kSlotRows + lane] = pre;
+    if (lane == 0)
+        slot[0] = mn | (mx << 16);
+    return tot;
+}
+
+// Write the records of tile t (counted by wave_count_tile) at rec[o...], one
+// wave, canonical order: position inside the tile (x fastest), then b.
+__device__ void wave_write_tile(const Geom& g, const unsigned short* __restrict__ lab, unsigned t, WaveEmit& W,
+                                const unsigned* __restrict__ slot, uint2* __restrict__ rec, unsigned o)
+{
+    const int lane = lane_id();
+    TileInfo ti = tile_info(g, t);
+    const unsigned hdr = slot[0];
+    if ((hdr & 0xffffu) != 0xffffu) {
+        const unsigned lo = hdr & 0xffffu, hi = hdr >> 16;
+        unsigned word = lane < ti.TY * ti.TZ ? slot[1 + lane] : 0u;
+        unsigned pb = word & 0xffffu, own_lo = word >> 16;
+        unsigned tot;
+        unsigned oo = o + wave_excl_scan_u((unsigned)__popc(pb), tot);
+        int y = ti.ty * ti.TY + (lane & (ti.TY - 1)), z = ti.tz * ti.TZ + (lane >> g.tsy);
+        while (pb) {
+            int lx = __ffs(pb) - 1;
+            pb &= pb - 1;
+            bool isl = (own_lo >> lx) & 1u;
+            unsigned own = isl ? lo : hi, oth = isl ? hi : lo;
+            rec[oo++] = make_uint2(pack(g, ti.tx * ti.TX + lx, y, z), own | (oth << 16));
+        }
+        return;
     }
     // several labels: enumerate distinct neighbour labels per pixel
+    wave_load_box(g, lab, W.box, ti);
+    const int BXY = ti.BX * ti.BY, zr = ti.hz;
     const int nv = ti.TX * ti.TY * ti.TZ;
-    const int per = (nv + kBlock - 1) / kBlock;  // contiguous run of voxels per thread
-    const int v0 = threadIdx.x * per, v1 = min(v0 + per, nv);
+    const int per = (nv + 63) / 64;  // contiguous run of voxels per lane
+    const int v0 = lane * per, v1 = min(v0 + per, nv);
     unsigned cc = 0;
     for (int v = v0; v < v1; ++v) {
         int lx = v & (ti.TX - 1), ly = (v >> g.tsx) & (ti.TY - 1), lz = v >> (g.tsx + g.tsy);
@@ -418,27 +496,24 @@ __device__ unsigned emit_tile(const Geom& g, const unsigned short* __restrict__ 
             continue;
         int cidx = (lx + 1) + ti.BX * ((ly + 1) + ti.BY * (lz + ti.hz));
         int lo, hi;
-        cc += neighbour_span(L.box, cidx, ti.BX, BXY, zr, L.box[cidx], lo, hi);
+        cc += neighbour_span(W.box, cidx, ti.BX, BXY, zr, W.box[cidx], lo, hi);
     }
     unsigned tot;
-    unsigned oo = o + block_exscan_u(cc, L.red, &tot);
-    if (WRITE) {
-        for (int v = v0; v < v1; ++v) {
-            int lx = v & (ti.TX - 1), ly = (v >> g.tsx) & (ti.TY - 1), lz = v >> (g.tsx + g.tsy);
-            int x = ti.tx * ti.TX + lx, y = ti.ty * ti.TY + ly, z = ti.tz * ti.TZ + lz;
-            if (x >= g.nx || y >= g.ny || z >= g.nz)
-                continue;
-            int cidx = (lx + 1) + ti.BX * ((ly + 1) + ti.BY * (lz + ti.hz));
-            int own = L.box[cidx];
-            unsigned pos = pack(g, x, y, z);
-            int l = neighbour_next(L.box, cidx, ti.BX, BXY, zr, own, -1);
-            while (l != 0x10000) {
-                rec[oo++] = make_uint2(pos, (unsigned)own | ((unsigned)l << 16));
-                l = neighbour_next(L.box, cidx, ti.BX, BXY, zr, own, l);
-            }
+    unsigned oo = o + wave_excl_scan_u(cc, tot);
+    for (int v = v0; v < v1; ++v) {
+        int lx = v & (ti.TX - 1), ly = (v >> g.tsx) & (ti.TY - 1), lz = v >> (g.tsx + g.tsy);
+        int x = ti.tx * ti.TX + lx, y = ti.ty * ti.TY + ly, z = ti.tz * ti.TZ + lz;
+        if (x >= g.nx || y >= g.ny || z >= g.nz)
+            continue;
+        int cidx = (lx + 1) + ti.BX * ((ly + 1) + ti.BY * (lz + ti.hz));
+        int own = W.box[cidx];
+        unsigned pos = pack(g, x, y, z);
+        int l = neighbour_next(W.box, cidx, ti.BX, BXY, zr, own, -1);
+        while (l != 0x10000) {
+            rec[oo++] = make_uint2(pos, (unsigned)own | ((unsigned)l << 16));
+            l = neighbour_next(W.box, cidx, ti.BX, BXY, zr, own, l);
         }
     }
-    return tot;
 }
 
 // Emission ranges: range r holds tiles [r*Re, (r+1)*Re) (Re = 2^lgRe <=
@@ -446,6 +521,14 @@ __device__ unsigned emit_tile(const Geom& g, const unsigned short* __restrict__ 
 // pixel this iteration, or every tile at initialisation) are shared among the
 // blocks round-robin -- block b takes tiles t = b (mod gridDim) -- so that a
 // surface crossing many neighbouring tiles does not pile up on one block.
+// Tiles are dealt to emission blocks through the permutation j -> j*C mod
+// ntiles (C coprime with ntiles), so that a surface crossing a run of
+// neighbouring tiles spreads over many blocks.
+__device__ __forceinline__ unsigned deal_tile(const Geom& g, unsigned j)
+{
+    return (unsigned)(((unsigned long long)j * (unsigned)g.deal) % (unsigned)g.ntiles);
+}
+
 __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned epoch, int all_dirty)
 {
     return all_dirty || b.dirty[t] == epoch;
@@ -455,7 +538,7 @@ __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned e
 // Clean tiles keep their previous count.
 __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int gated, int all_dirty)
 {
-    __shared__ EmitLds L;
+    __shared__ WaveEmit W[kBlock / 64];
     __shared__ unsigned s_dl[kBlock];
     __shared__ unsigned s_ndl;
     if (gated && stopped(b.ds))
@@ -465,8 +548,9 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
     if (threadIdx.x == 0)
         s_ndl = 0;
     __syncthreads();
-    const unsigned t = blockIdx.x + threadIdx.x * G;  // at most Re <= kBlock tiles per block
-    if (t < (unsigned)g.ntiles) {
+    const unsigned j = blockIdx.x + threadIdx.x * G;  // at most Re <= kBlock tiles per block
+    const unsigned t = deal_tile(g, j);
+    if (j < (unsigned)g.ntiles) {
         if (tile_dirty(b, t, epoch, all_dirty)) {
             s_dl[atomicAdd(&s_ndl, 1u)] = t;
         } else {
@@ -480,10 +564,11 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
     }
     __syncthreads();
     const unsigned ndl = s_ndl;
-    for (unsigned i = 0; i < ndl; ++i) {
-        unsigned td = s_dl[i];
-        unsigned cc = emit_tile<false>(g, b.lab, td, L, nullptr, 0);
-        if (threadIdx.x == 0) {
+    const int wv = threadIdx.x >> 6;
+    for (unsigned i = wv; i < ndl; i += kBlock / 64) {
+        const unsigned td = s_dl[i];
+        unsigned cc = wave_count_tile(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
+        if (lane_id() == 0) {
             b.tcnt[td] = cc;
             if (cc) {
                 atomicAdd(&b.part_cnt[td >> g.lgRe], cc);
@@ -515,42 +600,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
     if (gated && stopped(ds))
         return;
     const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    unsigned nf = 0;
-    if (!is_init) {
-        unsigned f = 0;
-        for (int i = tid; i < g.gp; i += kScanThreads)
-            f += b.part_f[i];
-        f = wave_sum(f);
-        if (lane == 0)
-            s_f[w] = f;
-        if (g.small_m && w < g.max_labels) {
-            long long dn = 0, dq = 0;
-            for (int i = lane; i < g.gp; i += 64) {
-                dn += b.part_n[(long long)w * g.gp + i];
-                dq += b.part_q[(long long)w * g.gp + i];
-            }
-            dn = wave_sum(dn);
-            dq = wave_sum(dq);
-            if (lane == 0) {
-                b.st_n[w] += dn;
-                b.st_s1[w] += dq;
-            }
-        }
-        __syncthreads();
-        for (int i = 0; i < kScanThreads / 64; ++i)
-            nf += s_f[i];
-    }
-    // per-label table of the piecewise-constant data term
-    for (int l = tid; l < g.max_labels; l += kScanThreads) {
-        long long n = b.st_n[l];
-        double dn = (double)n;
-        float mu = n > 0 ? (float)((double)b.st_s1[l] * g.fx_inv / dn) : 0.f;
-        float fa = n > 1 ? (float)(dn / (dn - 1.0)) : 0.f;
-        float fb = (float)(dn / (dn + 1.0));
-        b.lstat[l] = make_float4(mu, fa, fb, 0.f);
-    }
-    // exclusive scan of the emission partials (a contiguous chunk per thread)
-    const int per = (g.ge + kScanThreads - 1) / kScanThreads;
+    // every load is issued up front; the work below waits on them once
+    const int per = (g.ge + kScanThreads - 1) / kScanThreads;  // emission partials per thread (<= 2 typ.)
     const int i0 = tid * per, i1 = min(i0 + per, g.ge);
     unsigned long long sum = 0;
     unsigned nz = 0;
@@ -558,6 +609,60 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
         sum += b.part_cnt[i];
         nz += b.part_act[i];
     }
+    unsigned f = 0;
+    long long dn = 0, dq = 0, n0 = 0, q0 = 0;
+    const bool label_wave = g.small_m && w < g.max_labels;
+    if (!is_init) {
+        for (int i = tid; i < g.gp; i += kScanThreads)
+            f += b.part_f[i];
+        if (label_wave) {
+            const long long* pn = b.part_n + (long long)w * g.gp;
+            const long long* pq = b.part_q + (long long)w * g.gp;
+#pragma unroll 4
+            for (int i = lane; i < g.gp; i += 64) {
+                dn += pn[i];
+                dq += pq[i];
+            }
+        }
+    }
+    if (label_wave && lane == 0) {
+        n0 = b.st_n[w];
+        q0 = b.st_s1[w];
+    }
+    // flips, and statistics of few labels: one wave per label
+    unsigned nf = 0;
+    if (!is_init) {
+        f = wave_sum(f);
+        if (lane == 0)
+            s_f[w] = f;
+    }
+    if (label_wave) {
+        dn = wave_sum(dn);
+        dq = wave_sum(dq);
+        if (lane == 0) {
+            long long n = n0 + dn, q = q0 + dq;
+            if (!is_init) {
+                b.st_n[w] = n;
+                b.st_s1[w] = q;
+            }
+            double d = (double)n;
+            float mu = n > 0 ? (float)((double)q * g.fx_inv / d) : 0.f;
+            float fa = n > 1 ? (float)(d / (d - 1.0)) : 0.f;
+            float fb = (float)(d / (d + 1.0));
+            b.lstat[w] = make_float4(mu, fa, fb, 0.f);
+        }
+    }
+    if (!g.small_m) {  // statistics already final (atomics in k_flip)
+        for (int l = tid; l < g.max_labels; l += kScanThreads) {
+            long long n = b.st_n[l];
+            double d = (double)n;
+            float mu = n > 0 ? (float)((double)b.st_s1[l] * g.fx_inv / d) : 0.f;
+            float fa = n > 1 ? (float)(d / (d - 1.0)) : 0.f;
+            float fb = (float)(d / (d + 1.0));
+            b.lstat[l] = make_float4(mu, fa, fb, 0.f);
+        }
+    }
+    // exclusive scan of the emission partials
     unsigned long long isum = sum;
     unsigned inz = nz;
     for (int o = 1; o < 64; o <<= 1) {
@@ -573,6 +678,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
         s_nz[w] = inz;
     }
     __syncthreads();
+    if (!is_init)
+        for (int i = 0; i < kScanThreads / 64; ++i)
+            nf += s_f[i];
     unsigned long long off = 0, total = 0;
     unsigned offz = 0, totz = 0;
     for (int i = 0; i < kScanThreads / 64; ++i) {
@@ -583,18 +691,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
     }
     off += isum - sum;
     offz += inz - nz;
-    bool overflow = total > (unsigned long long)b.cap;
-    if (!overflow) {
-        for (int i = i0; i < i1; ++i) {
+    const bool overflow = total > (unsigned long long)b.cap;
+    for (int i = i0; i < i1; ++i) {
+        unsigned c = b.part_cnt[i], z = b.part_act[i];
+        if (!overflow) {
             b.part_off[i] = (unsigned)off;
             b.part_aoff[i] = offz;
-            off += b.part_cnt[i];
-            offz += b.part_act[i];
         }
-    }
-    __syncthreads();
-    for (int i = i0; i < i1; ++i) {  // the next count accumulates afresh
-        b.part_cnt[i] = 0;
+        off += c;
+        offz += z;
+        b.part_cnt[i] = 0;  // the next count accumulates afresh
         b.part_act[i] = 0;
     }
     if (overflow && !is_init) {
@@ -665,7 +771,8 @@ __device__ __forceinline__ bool decide_move(const uint2* rec, const float* grad,
 __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* img, int cur, int nxt,
                                                  const float* __restrict__ grad, int all_dirty)
 {
-    __shared__ EmitLds L;
+    __shared__ WaveEmit W[kBlock / 64];
+    __shared__ unsigned s_red[kBlock / 64];
     __shared__ unsigned s_pre[kBlock + 1];
     __shared__ unsigned s_old[kBlock];
     __shared__ unsigned s_dl[kBlock];
@@ -704,8 +811,8 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     const unsigned c = in ? b.tcnt[t] : 0;
     const bool dirty = in && tile_dirty(b, (unsigned)t, epoch, all_dirty);
     unsigned tot, totz;
-    const unsigned ex = block_exscan_u(c, L.red, &tot);
-    const unsigned exz = block_exscan_u(c != 0 ? 1u : 0u, L.red, &totz);
+    const unsigned ex = block_exscan_u(c, s_red, &tot);
+    const unsigned exz = block_exscan_u(c != 0 ? 1u : 0u, s_red, &totz);
     const unsigned base = b.part_off[blockIdx.x], abase = b.part_aoff[blockIdx.x];
     if (in) {
         b.tstart[nxt][t] = base + ex;
@@ -748,18 +855,22 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     }
     // dirty tiles of this block's round-robin share are re-emitted from the labels
     const unsigned G = gridDim.x;
-    const unsigned td = blockIdx.x + threadIdx.x * G;
-    if (td < (unsigned)g.ntiles && b.tcnt[td] && tile_dirty(b, td, epoch, all_dirty))
+    const unsigned jd = blockIdx.x + threadIdx.x * G;
+    const unsigned td = deal_tile(g, jd);
+    if (jd < (unsigned)g.ntiles && b.tcnt[td] && tile_dirty(b, td, epoch, all_dirty))
         s_dl[atomicAdd(&s_ndl, 1u)] = td;
     __syncthreads();
     const unsigned ndl = s_ndl;
-    for (unsigned i = 0; i < ndl; ++i) {
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    for (unsigned i = wv; i < ndl; i += kBlock / 64) {
         const unsigned tt = s_dl[i];
         const int r0 = (int)(tt >> g.lgRe) << g.lgRe;
         // offset of tile tt: its range's base plus the counts before it in the range
-        unsigned part = (r0 + (int)threadIdx.x < (int)tt) ? b.tcnt[r0 + threadIdx.x] : 0u;
-        unsigned o = b.part_off[tt >> g.lgRe] + block_sum_u(part, L.red);
-        emit_tile<true>(g, b.lab, tt, L, rec, o);
+        unsigned part = 0;
+        for (int k = r0 + lane; k < (int)tt; k += 64)
+            part += b.tcnt[k];
+        unsigned o = b.part_off[tt >> g.lgRe] + wave_sum_u(part);
+        wave_write_tile(g, b.lab, tt, W[wv], b.tslot + (size_t)tt * kSlotWords, rec, o);
     }
 }
 
@@ -1061,19 +1172,20 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
 {
     using S = BrickShape<ND, H>;
     constexpr TapList<S::NT> taps = make_taps<ND, H>();
+    constexpr int NCORE = S::TX * S::TY * S::TZ;
     __shared__ __align__(16) char lds[brick_lds_bytes(ND, H)];
-    __shared__ unsigned s_flag;
-    __shared__ unsigned s_beg[32];
-    __shared__ unsigned s_pre[33];
-    float2* s_v = (float2*)lds;                      // (value of lo->hi, value of hi->lo)
-    unsigned* s_n = (unsigned*)(s_v + S::NCELL);     // count of lo->hi | count of hi->lo << 16
+    __shared__ unsigned s_core[NCORE];          // own particles: brick corner cell | side A << 31
+    __shared__ unsigned s_beg[32], s_tile[32], s_lxy[32], s_lz[32], s_rpre[33];
+    __shared__ unsigned s_mode, s_ncore;
+    float2* s_v = (float2*)lds;                   // (value of a lo->hi particle, value of a hi->lo particle)
+    unsigned* s_n = (unsigned*)(s_v + S::NCELL);  // their counts, packed lo->hi | hi->lo << 16
     DevState* ds = b.ds;
     if (gated && stopped(ds))
         return;
     unsigned a0, a1;
     xcd_chunk(ds->n_active[cur], a0, a1);
     const unsigned* ts = b.tstart[cur];
-    const uint2* rec = b.rec[cur];
+    const int lane = lane_id();
     for (unsigned ai = a0; ai < a1; ++ai) {
         const unsigned t = b.active[cur][ai];
         const int tx = (int)(t % (unsigned)g.ntx), ty = (int)((t / (unsigned)g.ntx) % (unsigned)g.nty);
@@ -1082,110 +1194,146 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
         const int bx0 = max(ox, 0), bx1 = min(ox + S::BX, g.nx);
         const int by0 = max(oy, 0), by1 = min(oy + S::BY, g.ny);
         const int bz0 = max(oz, 0), bz1 = min(oz + S::BZ, g.nz);
-        const int kx0 = bx0 >> g.tsx, nkx = ((bx1 - 1) >> g.tsx) - kx0 + 1;
-        const int ky0 = by0 >> g.tsy, nky = ((by1 - 1) >> g.tsy) - ky0 + 1;
-        const int kz0 = bz0 >> g.tsz, nkz = ((bz1 - 1) >> g.tsz) - kz0 + 1;
+        const int kx0 = bx0 / S::TX, nkx = (bx1 - 1) / S::TX - kx0 + 1;
+        const int ky0 = by0 / S::TY, nky = (by1 - 1) / S::TY - ky0 + 1;
+        const int kz0 = bz0 / S::TZ, nkz = (bz1 - 1) / S::TZ - kz0 + 1;
         const int nnt = nkx * nky * nkz;
-        const unsigned cs = ts[t], ce = ts[t + 1];
-        const unsigned code0 = rec[cs].y;
-        const unsigned lo = min(code0 & 0xffffu, code0 >> 16), hi = max(code0 & 0xffffu, code0 >> 16);
-        const unsigned codeA = lo | (hi << 16), codeB = hi | (lo << 16);
+        const int kown = (tx - kx0) + nkx * ((ty - ky0) + nky * (tz - kz0));
         __syncthreads();  // the previous tile is done with LDS
+        // wave 0: the neighbour tiles' record ranges, slot headers and the
+        // rows of each that fall inside the box; meanwhile the brick is cleared
+        if (threadIdx.x < 64) {
+            unsigned beg = 0, hdr = 0, nrow = 0, lxy = 0, lzr = 0, tile = 0;
+            bool has = false;
+            if (lane < nnt) {
+                const int kx = kx0 + lane % nkx, ky = ky0 + (lane / nkx) % nky, kz = kz0 + lane / (nkx * nky);
+                tile = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
+                beg = ts[tile];
+                has = ts[tile + 1] > beg;
+                if (has)
+                    hdr = b.tslot[(size_t)tile * kSlotWords];
+                const int lx0 = max(bx0 - kx * S::TX, 0), lx1 = min(bx1 - kx * S::TX, S::TX);
+                const int ly0 = max(by0 - ky * S::TY, 0), ly1 = min(by1 - ky * S::TY, S::TY);
+                const int lz0 = max(bz0 - kz * S::TZ, 0), lz1 = min(bz1 - kz * S::TZ, S::TZ);
+                lxy = (unsigned)lx0 | ((unsigned)lx1 << 8) | ((unsigned)ly0 << 16) | ((unsigned)ly1 << 24);
+                lzr = (unsigned)lz0 | ((unsigned)lz1 << 8);
+                nrow = has ? (unsigned)((ly1 - ly0) * (lz1 - lz0)) : 0u;
+            }
+            const unsigned own_hdr = __shfl(hdr, kown);
+            const bool bad = has && (hdr != own_hdr || (hdr & 0xffffu) == 0xffffu);
+            unsigned tot;
+            const unsigned rp = wave_excl_scan_u(nrow, tot);
+            const bool any_bad = __ballot(bad) != 0;  // whole wave votes
+            if (lane < nnt) {
+                s_beg[lane] = beg;
+                s_tile[lane] = tile;
+                s_lxy[lane] = lxy;
+                s_lz[lane] = lzr;
+                s_rpre[lane] = rp;
+            }
+            if (lane == 0) {
+                s_rpre[nnt] = tot;
+                s_mode = any_bad ? 1u : 0u;
+            }
+        }
         for (int k = threadIdx.x; k < S::NCELL; k += kSobBlock) {
             s_v[k] = make_float2(0.f, 0.f);
             s_n[k] = 0u;
         }
-        if (threadIdx.x == 0)
-            s_flag = 0;
-        if ((int)threadIdx.x < nnt) {
-            int k = threadIdx.x;
-            int kx = kx0 + k % nkx, ky = ky0 + (k / nkx) % nky, kz = kz0 + k / (nkx * nky);
-            unsigned nt = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
-            s_beg[k] = ts[nt];
-            s_pre[k + 1] = ts[nt + 1] - ts[nt];
-        }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            s_pre[0] = 0;
-            for (int k = 0; k < nnt; ++k)
-                s_pre[k + 1] += s_pre[k];
-        }
-        __syncthreads();
-        // scatter the box's particles into the brick, 8 loads in flight per thread
-        const unsigned total = s_pre[nnt];
-        int j = 0;  // neighbour tile of this thread's flat index (monotone)
-        for (unsigned k0 = 0; k0 < total; k0 += 8 * kSobBlock) {
-            uint2 r[8];
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                unsigned k = k0 + u * kSobBlock + threadIdx.x;
-                r[u] = make_uint2(0xffffffffu, 0u);
-                v[u] = 0.f;
-                if (k < total) {
-                    while (s_pre[j + 1] <= k)
-                        ++j;
-                    unsigned q = s_beg[j] + (k - s_pre[j]);
-                    r[u] = rec[q];
-                    v[u] = in[q];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (r[u].x == 0xffffffffu)
-                    continue;
-                int x, y, z;
-                unpack(g, r[u].x, x, y, z);
-                if (x < bx0 || x >= bx1 || y < by0 || y >= by1 || z < bz0 || z >= bz1)
-                    continue;
-                int c = (x - ox) + S::BX * ((y - oy) + S::BY * (z - oz));
-                if (r[u].y == codeA) {
-                    s_v[c] = make_float2(v[u], 0.f);
-                    s_n[c] = 1u;
-                } else if (r[u].y == codeB) {
-                    s_v[c] = make_float2(0.f, v[u]);
-                    s_n[c] = 1u << 16;
-                } else {
-                    s_flag = 1;
-                }
-            }
-        }
-        __syncthreads();
-        if (s_flag) {
+        if (s_mode) {  // several label pairs around this tile: staged scan over records
             sob_generic_tile(g, b, cur, in, out, t, lds);
             continue;
         }
-        // stencil: uniform trip count, idle lanes work on the tile's first particle
-        for (unsigned base = cs; base < ce; base += kSobBlock) {
-            const unsigned p = base + threadIdx.x;
-            const bool act = p < ce;
-            const uint2 r = rec[act ? p : cs];
-            int x, y, z;
-            unpack(g, r.x, x, y, z);
-            const int c0 = (x - ox - H) + S::BX * ((y - oy - H) + S::BY * (z - oz - S::HZ));
+        // rows of the box: read the particle bits from the tiles' slots and
+        // scatter the L2 gradients of exactly the box's particles
+        const unsigned nrows = s_rpre[nnt];
+        int k = 0;  // neighbour tile of this thread's row (monotone)
+        for (unsigned ri = threadIdx.x; ri < nrows; ri += kSobBlock) {
+            while (s_rpre[k + 1] <= ri)
+                ++k;
+            const unsigned i = ri - s_rpre[k];
+            const unsigned lxy = s_lxy[k], lzr = s_lz[k];
+            const int lx0 = lxy & 0xff, lx1 = (lxy >> 8) & 0xff, ly0 = (lxy >> 16) & 0xff, ly1 = lxy >> 24;
+            const int ny = ly1 - ly0;
+            const int ly = ly0 + (int)(i % (unsigned)ny), lz = (int)(lzr & 0xff) + (int)(i / (unsigned)ny);
+            const int row = ly + S::TY * lz;
+            const unsigned* sl = b.tslot + (size_t)s_tile[k] * kSlotWords;
+            const unsigned word = sl[1 + row], pre = sl[1 + kSlotRows + row];
+            const unsigned xm = ((1u << lx1) - 1u) & ~((1u << lx0) - 1u);
+            const unsigned pbits = word & 0xffffu, own = word >> 16;
+            const unsigned bits = pbits & xm;
+            unsigned idx = s_beg[k] + pre + (unsigned)__popc(pbits & ((1u << lx0) - 1u));
+            const int kx = (int)(s_tile[k] % (unsigned)g.ntx);
+            const int cbase = (kx * S::TX - ox) + S::BX * ((ly + ((int)(s_tile[k] / (unsigned)g.ntx) % g.nty) * S::TY - oy) +
+                                                           S::BY * (lz + (int)(s_tile[k] / ((unsigned)g.ntx * (unsigned)g.nty)) * S::TZ - oz));
+            float v[S::TX];
+#pragma unroll
+            for (int lx = 0; lx < S::TX; ++lx) {
+                v[lx] = 0.f;
+                if ((bits >> lx) & 1u)
+                    v[lx] = in[idx++];
+            }
+#pragma unroll
+            for (int lx = 0; lx < S::TX; ++lx) {
+                if ((bits >> lx) & 1u) {
+                    const int c = cbase + lx;
+                    if ((own >> lx) & 1u) {
+                        s_v[c] = make_float2(v[lx], 0.f);
+                        s_n[c] = 1u;
+                    } else {
+                        s_v[c] = make_float2(0.f, v[lx]);
+                        s_n[c] = 1u << 16;
+                    }
+                }
+            }
+        }
+        // the tile's own particles, in record order, as (brick corner cell, side)
+        if (threadIdx.x < 64) {
+            const unsigned* sl = b.tslot + (size_t)t * kSlotWords;
+            unsigned word = 0, pre = 0;
+            if (lane < S::TY * S::TZ) {
+                word = sl[1 + lane];
+                pre = sl[1 + kSlotRows + lane];
+            }
+            unsigned pbits = word & 0xffffu;
+            const unsigned own = word >> 16;
+            const int ly = lane & (S::TY - 1), lz = lane / S::TY;
+            while (pbits) {
+                const int lx = __ffs(pbits) - 1;
+                pbits &= pbits - 1;
+                s_core[pre++] = (unsigned)(lx + S::BX * (ly + S::BY * lz)) | (((own >> lx) & 1u) << 31);
+            }
+            if (lane == 0)
+                s_ncore = ts[t + 1] - ts[t];
+        }
+        __syncthreads();
+        const unsigned cs = ts[t], ncore = s_ncore;
+        for (unsigned e = threadIdx.x; e < ncore; e += kSobBlock) {
+            const unsigned ce = s_core[e];
+            const int c0 = (int)(ce & 0x7fffffffu);
+            const bool sideA = (ce >> 31) != 0;
             const float2* vb = s_v + c0;
-            const unsigned* nb = s_n + c0;
+            const unsigned* nbp = s_n + c0;
             float sA = 0.f, sB = 0.f;
             unsigned cnt = 0;
 #pragma unroll
-            for (int k = 0; k < S::NT; ++k) {
-                const float2 cv = vb[taps.off[k]];
-                const float wk = sw.w[taps.d2[k]];
+            for (int q = 0; q < S::NT; ++q) {
+                const float2 cv = vb[taps.off[q]];
+                const float wk = sw.w[taps.d2[q]];
                 sA = fmaf(wk, cv.x, sA);
                 sB = fmaf(wk, cv.y, sB);
                 if (FULL)
-                    cnt += nb[taps.off[k]];
+                    cnt += nbp[taps.off[q]];
                 else
-                    cnt += nb[taps.off[k]] * sw.m[taps.d2[k]];
+                    cnt += nbp[taps.off[q]] * sw.m[taps.d2[q]];
             }
-            const bool sideA = r.y == codeA;
             const float same = sideA ? sA : sB, other = sideA ? sB : sA;
             const unsigned nS = sideA ? (cnt & 0xffffu) : (cnt >> 16), nO = sideA ? (cnt >> 16) : (cnt & 0xffffu);
             float res = same / (float)nS;
             if (nO)
                 res -= other / (float)nO;
-            if (act)
-                out[p] = res;
+            out[cs + e] = res;
         }
     }
 }
@@ -1444,10 +1592,10 @@ hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur,
 }
 
 hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* in, float* out,
-                          int gated, hipStream_t s)
+                          int gated, int use_slots, hipStream_t s)
 {
     dim3 gd(g.sob_grid), bd(kSobBlock);
-    if (!g.brick) {
+    if (!g.brick || !use_slots) {
         hipLaunchKernelGGL(k_sobolev_generic, gd, bd, g.sob_lds, s, g, b, cur, in, out, gated);
         return hipGetLastError();
     }
