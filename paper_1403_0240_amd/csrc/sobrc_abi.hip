@@ -126,6 +126,7 @@ Geom make_geom(const sobrc_params* p)
     g.max_labels = p->max_labels;
     g.small_m = p->max_labels <= kSmallM;
     long long gp = (p->max_particles + kBlock - 1) / kBlock;
+    gp = gp < 8 ? gp : (gp + 7) / 8 * 8;  // whole rounds over the 8 XCDs
     g.gp = (int)(gp < 1 ? 1 : (gp > kMaxGrid ? kMaxGrid : gp));
     // emission ranges of Re = 2^lgRe tiles, at most kMaxGrid ranges unless a
     // range would exceed kBlock tiles
@@ -134,23 +135,6 @@ Geom make_geom(const sobrc_params* p)
         ++g.lgRe;
     g.Re = 1 << g.lgRe;
     g.ge = (g.ntiles + g.Re - 1) >> g.lgRe;
-    // a multiplier near ntiles * (golden ratio - 1) that is coprime with ntiles
-    {
-        unsigned long long c = (unsigned long long)((double)g.ntiles * 0.6180339887) | 1ull;
-        auto gcd = [](unsigned long long x, unsigned long long y) {
-            while (y) {
-                unsigned long long r = x % y;
-                x = y;
-                y = r;
-            }
-            return x;
-        };
-        while (g.ntiles > 1 && gcd(c, (unsigned long long)g.ntiles) != 1)
-            c += 2;
-        g.deal = (unsigned)(g.ntiles > 1 ? c % (unsigned long long)g.ntiles : 0);
-        if (g.ntiles > 1 && g.deal == 0)
-            g.deal = 1;
-    }
     // Sobolev kernel: dense LDS brick for (ndim, h) when instantiated, else
     // the generic staged scan
     g.brick = g.h >= 1 && g.h <= (g.ndim == 3 ? kBrickMaxH3 : kBrickMaxH2);

@@ -71,7 +71,6 @@ struct Geom {
     int small_m;                // max_labels <= kSmallM
     int gp;                     // blocks of the particle kernels (l2diff, flip)
     int ge, Re, lgRe;           // emission ranges: count, tiles per range (2^lgRe)
-    unsigned deal;              // multiplier coprime with ntiles dealing dirty tiles to blocks
     int brick;                  // Sobolev brick kernel for (ndim, h) exists
     int full;                   // T == (h+1)^2: every offset of the brick stencil is inside
     int stage_cap;              // generic-path staging capacity

@@ -518,15 +518,19 @@ __device__ void wave_write_tile(const Geom& g, const unsigned short* __restrict_
 
 // Emission ranges: range r holds tiles [r*Re, (r+1)*Re) (Re = 2^lgRe <=
 // kBlock); the scan works on per-range totals.  Dirty tiles (a flip within one
-// pixel this iteration, or every tile at initialisation) are shared among the
-// blocks round-robin -- block b takes tiles t = b (mod gridDim) -- so that a
-// surface crossing many neighbouring tiles does not pile up on one block.
-// Tiles are dealt to emission blocks through the permutation j -> j*C mod
-// ntiles (C coprime with ntiles), so that a surface crossing a run of
-// neighbouring tiles spreads over many blocks.
-__device__ __forceinline__ unsigned deal_tile(const Geom& g, unsigned j)
+// pixel this iteration, or every tile at initialisation) are re-emitted one
+// wave per tile.  Slot j (block j mod gridDim) takes tile
+//   t = s * Ls + u,   s = j mod 8,  u = j / 8,  Ls = ceil(ntiles / 8),
+// so with a grid that is a multiple of 8 every XCD works on one contiguous
+// eighth of the tile order (neighbouring tiles share label rows, and so lines
+// of that XCD's L2), while consecutive tiles go to consecutive blocks of the
+// XCD (a surface crossing a run of tiles spreads over many blocks).
+__device__ __forceinline__ bool slot_tile(const Geom& g, unsigned j, unsigned& t)
 {
-    return (unsigned)(((unsigned long long)j * (unsigned)g.deal) % (unsigned)g.ntiles);
+    const unsigned ls = ((unsigned)g.ntiles + 7u) >> 3;
+    const unsigned u = j >> 3;
+    t = (j & 7u) * ls + u;
+    return u < ls && t < (unsigned)g.ntiles;
 }
 
 __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned epoch, int all_dirty)
@@ -548,9 +552,9 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
     if (threadIdx.x == 0)
         s_ndl = 0;
     __syncthreads();
-    const unsigned j = blockIdx.x + threadIdx.x * G;  // at most Re <= kBlock tiles per block
-    const unsigned t = deal_tile(g, j);
-    if (j < (unsigned)g.ntiles) {
+    const unsigned j = blockIdx.x + threadIdx.x * G;  // G * kBlock >= 8 * ceil(ntiles / 8)
+    unsigned t;
+    if (slot_tile(g, j, t)) {
         if (tile_dirty(b, t, epoch, all_dirty)) {
             s_dl[atomicAdd(&s_ndl, 1u)] = t;
         } else {
@@ -856,8 +860,8 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     // dirty tiles of this block's round-robin share are re-emitted from the labels
     const unsigned G = gridDim.x;
     const unsigned jd = blockIdx.x + threadIdx.x * G;
-    const unsigned td = deal_tile(g, jd);
-    if (jd < (unsigned)g.ntiles && b.tcnt[td] && tile_dirty(b, td, epoch, all_dirty))
+    unsigned td;
+    if (slot_tile(g, jd, td) && b.tcnt[td] && tile_dirty(b, td, epoch, all_dirty))
         s_dl[atomicAdd(&s_ndl, 1u)] = td;
     __syncthreads();
     const unsigned ndl = s_ndl;
@@ -872,6 +876,18 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
         unsigned o = b.part_off[tt >> g.lgRe] + wave_sum_u(part);
         wave_write_tile(g, b.lab, tt, W[wv], b.tslot + (size_t)tt * kSlotWords, rec, o);
     }
+}
+
+// Items [a0, a1) of [0, na) for this block: contiguous chunks, consecutive
+// chunks on the same XCD (blocks are dealt to the 8 XCDs round-robin), so
+// that work on neighbouring tiles shares one L2.  Grids that are not a
+// multiple of 8 take chunks in block order.
+__device__ __forceinline__ void xcd_chunk(unsigned na, unsigned& a0, unsigned& a1)
+{
+    const unsigned G = gridDim.x;
+    const unsigned L = (G & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    a0 = (unsigned)((unsigned long long)L * na / G);
+    a1 = (unsigned)((unsigned long long)(L + 1) * na / G);
 }
 
 // --------------------------------------------------- L2 gradient per particle
@@ -894,7 +910,9 @@ __global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* i
     unsigned n = ds->n[cur];
     const uint2* rec = b.rec[cur];
     long long nxy = (long long)g.nx * g.ny;
-    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
+    unsigned p0, p1;
+    xcd_chunk(n, p0, p1);
+    for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
         uint2 r = rec[p];
         int x, y, z;
         unpack(g, r.x, x, y, z);
@@ -1096,16 +1114,6 @@ __device__ void sob_generic_tile(const Geom& g, const Bufs& b, int cur, const fl
             out[p] = res;
         }
     }
-}
-
-// Tiles [a0, a1) of the non-empty list for this block: contiguous chunks,
-// consecutive chunks on the same XCD (blocks are dealt to the 8 XCDs
-// round-robin).
-__device__ __forceinline__ void xcd_chunk(unsigned na, unsigned& a0, unsigned& a1)
-{
-    const unsigned G = gridDim.x, L = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
-    a0 = (unsigned)((unsigned long long)L * na / G);
-    a1 = (unsigned)((unsigned long long)(L + 1) * na / G);
 }
 
 __global__ __launch_bounds__(kSobBlock) void k_sobolev_generic(Geom g, Bufs b, int cur,
@@ -1366,12 +1374,14 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
     const uint2* rec = b.rec[cur];
     const int lane = lane_id();
     const int TX = 1 << g.tsx, TY = 1 << g.tsy, TZ = 1 << g.tsz;
-    for (unsigned base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+    unsigned p0, p1;
+    xcd_chunk(n, p0, p1);
+    for (unsigned base = p0; base < p1; base += kBlock) {
         unsigned p = base + threadIdx.x;
         bool f = false;
         unsigned lin = 0;
         int a = 0, bb = 0;
-        if (p < n) {
+        if (p < p1) {
             uint2 r;
             if (decide_move(rec, grad, n, p, r, bb)) {
                 f = true;
