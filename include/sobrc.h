@@ -53,7 +53,11 @@ enum {
 };
 enum { SOBRC_F32 = 0, SOBRC_U16 = 1 };            /* image element type */
 enum { SOBRC_PC = 0, SOBRC_PS = 1 };              /* piecewise constant / smooth */
-enum { SOBRC_MODE_SOBOLEV = 0, SOBRC_MODE_L2 = 1 };
+/* Gradient mode of step/run.  AUTO: Sobolev gradients until the contour
+ * oscillates, L2-type gradients from then on (the paper's remark after
+ * Eq. (6) and its Fig. 3 experiment; the detection rule is this library's,
+ * see get_gradient_mode). */
+enum { SOBRC_MODE_SOBOLEV = 0, SOBRC_MODE_L2 = 1, SOBRC_MODE_AUTO = 2 };
 
 typedef struct {
     int32_t ndim;          /* 2 or 3 */
@@ -112,8 +116,8 @@ int32_t compute_l2_diff(sobrc_ctx* ctx, float* d_dE_l2, void* stream);
  * accumulation).  Asynchronous. */
 int32_t sobolev_smooth(sobrc_ctx* ctx, const float* d_dE_l2, float* d_dE_h1, void* stream);
 
-/* One iteration: L2 gradient, Sobolev update (mode SOBOLEV) or none (mode L2),
- * acceptance -- every particle with gradient < 0 is a candidate, per pixel the
+/* One iteration: L2 gradient, Sobolev update (mode SOBOLEV; mode AUTO until
+ * it has switched) or none (mode L2), acceptance -- every particle with gradient < 0 is a candidate, per pixel the
  * smallest gradient wins (ties: smaller b), all chosen moves applied together
  * -- then region statistics and the particle set are brought up to date.
  * If d_nflips != NULL the number of changed pixels is written there (device
@@ -150,10 +154,20 @@ int32_t get_labels(sobrc_ctx* ctx, int32_t* d_labels, void* stream);
 int32_t get_region_stats(sobrc_ctx* ctx, int64_t* h_count, double* h_sum, void* stream);
 
 /* Per-iteration telemetry of the last iterations (synchronises): for up to
- * `cap` most recent iterations, particle count N_t and flips_t, oldest first.
- * *h_len receives the number written. */
+ * `cap` most recent iterations, particle count N_t, flips_t and (h_reversals
+ * may be NULL) reversals_t -- flips of pixels that also changed in iteration
+ * t - 1 -- oldest first.  *h_len receives the number written. */
 int32_t get_history(sobrc_ctx* ctx, int32_t cap, int32_t* h_n, int32_t* h_flips,
-                    int32_t* h_len, void* stream);
+                    int32_t* h_reversals, int32_t* h_len, void* stream);
+
+/* Oscillation fallback of mode AUTO (synchronises).  Iteration t oscillates
+ * when flips_t > 0 and 2 * reversals_t >= flips_t.  An AUTO iteration t that
+ * oscillates right after an oscillating iteration t - 1 makes every later
+ * AUTO iteration use L2-type gradients; *h_switch_iter receives that first
+ * L2 iteration (counted from init_labels), or -1 while there is none.  The
+ * switch lasts until the next init_labels; iterations count from
+ * init_labels across step and run calls. */
+int32_t get_gradient_mode(sobrc_ctx* ctx, int32_t* h_switch_iter, void* stream);
 
 /* Stateless Eq. (6) on caller-given particles (any order, n >= 0): positions
  * as linear indices d_lin, labels d_a != d_b in [0, max_labels), values d_in;

@@ -16,7 +16,7 @@ SRC = os.path.join(HERE, "sobrc_oracle.c")
 LIB = os.path.join(HERE, "libsobrc_oracle.so")
 
 PC, PS = 0, 1
-MODE_SOBOLEV, MODE_L2 = 0, 1
+MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 NEIGH_BRUTE, NEIGH_CELLS = 0, 1
 
 
@@ -67,7 +67,9 @@ def lib():
                                C.c_void_p]
         L.ora_run.restype = C.c_int32
         L.ora_run.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
-                              C.c_double, C.c_void_p, C.c_void_p]
+                              C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_reversals.restype = C.c_int64
+        L.ora_reversals.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
         L.ora_energy_pc.restype = C.c_double
         L.ora_energy_pc.argtypes = [P(Params), C.c_void_p, C.c_void_p]
         L.ora_conv_closed_curve.restype = None
@@ -178,13 +180,30 @@ def step(P: Params, I, L, mode=MODE_SOBOLEV, want_arrays=True):
     return L, {"n": n, "flips": nf.value, "lin": lin, "a": a, "b": b, "dE_l2": g2, "dE_h1": g1}
 
 
-def run(P: Params, I, L, mode=MODE_SOBOLEV, max_iters=100, tol=0.0):
+def run_ex(P: Params, I, L, mode=MODE_SOBOLEV, max_iters=100, tol=0.0):
+    """ora_run with all telemetry: final labels, iterations done, per-iteration
+    N_t, flips and reversals, and the first L2 iteration of AUTO mode (-1)."""
     I = _img(I)
     L = _lab(L).copy()
     hn = np.zeros(max_iters, np.int64)
     hf = np.zeros(max_iters, np.int64)
-    t = lib().ora_run(C.byref(P), _ptr(I), _ptr(L), mode, max_iters, float(tol), _ptr(hn), _ptr(hf))
-    return L, t, hn[:t], hf[:t]
+    hb = np.zeros(max_iters, np.int64)
+    sw = C.c_int32(-1)
+    t = lib().ora_run(C.byref(P), _ptr(I), _ptr(L), mode, max_iters, float(tol), _ptr(hn), _ptr(hf),
+                      _ptr(hb), C.byref(sw))
+    return {"L": L, "t": t, "n": hn[:t], "flips": hf[:t], "reversals": hb[:t], "switch": sw.value}
+
+
+def run(P: Params, I, L, mode=MODE_SOBOLEV, max_iters=100, tol=0.0):
+    r = run_ex(P, I, L, mode, max_iters, tol)
+    return r["L"], r["t"], r["n"], r["flips"]
+
+
+def reversals(L_prev, L_next, stamp, t):
+    """ora_reversals on flat int32 label arrays; stamp (uint32) is updated in place."""
+    Lp, Ln = _lab(L_prev), _lab(L_next)
+    assert stamp.dtype == np.uint32 and stamp.flags.c_contiguous and stamp.size == Lp.size
+    return lib().ora_reversals(Lp.size, _ptr(Lp), _ptr(Ln), _ptr(stamp), int(t))
 
 
 def energy_pc(P: Params, I, L) -> float:

@@ -25,7 +25,11 @@
  *  - length prior: number of face-adjacent pixel pairs with different labels;
  *  - acceptance: every particle with gradient < 0 is a candidate, per pixel the
  *    smallest gradient wins (ties: smaller target label), all chosen moves are
- *    applied together (no topology control, no oscillation fallback).
+ *    applied together (no topology control);
+ *  - oscillation (AUTO mode): an iteration oscillates when at least half of
+ *    its flips revert pixels that changed in the iteration before; after two
+ *    oscillating iterations in a row, L2-type gradients are used from the
+ *    next iteration on (ora_reversals, ora_run).
  *
  * parity unpinned: whole-run segmentations against the paper's figures (the
  * paper's images are not available).
@@ -383,19 +387,53 @@ int64_t ora_step(const ora_params* P, const double* I, int32_t* L, int32_t mode,
     return ret;
 }
 
-int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
-                int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f)
+int64_t ora_reversals(int64_t nvox, const int32_t* L_prev, const int32_t* L_next,
+                      uint32_t* stamp, int64_t t)
 {
+    int64_t back = 0;
+    for (int64_t x = 0; x < nvox; ++x) {
+        if (L_prev[x] == L_next[x])
+            continue;
+        if (stamp[x] != 0 && stamp[x] == (uint32_t)t) /* changed in iteration t - 1 */
+            ++back;
+        stamp[x] = (uint32_t)(t + 1);
+    }
+    return back;
+}
+
+int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
+                int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f,
+                int64_t* hist_b, int32_t* switch_iter)
+{
+    int64_t nvox = (int64_t)P->nx * P->ny * P->nz;
+    int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * (size_t)nvox);
+    uint32_t* stamp = (uint32_t*)calloc((size_t)nvox, sizeof(uint32_t));
+    int32_t grad = mode == ORA_MODE_L2 ? ORA_MODE_L2 : ORA_MODE_SOBOLEV;
+    if (switch_iter)
+        *switch_iter = -1;
+    int osc_prev = 0;
     int32_t t = 0;
     while (t < max_iters) {
         int64_t flips = 0;
-        int64_t np = ora_step(P, I, L, mode, 0, NULL, NULL, NULL, NULL, NULL, &flips);
+        memcpy(prev, L, sizeof(int32_t) * (size_t)nvox);
+        int64_t np = ora_step(P, I, L, grad, 0, NULL, NULL, NULL, NULL, NULL, &flips);
+        int64_t back = ora_reversals(nvox, prev, L, stamp, t);
         if (hist_n) hist_n[t] = np;
         if (hist_f) hist_f[t] = flips;
+        if (hist_b) hist_b[t] = back;
+        int osc = flips > 0 && 2 * back >= flips;
+        if (mode == ORA_MODE_AUTO && grad == ORA_MODE_SOBOLEV && osc && osc_prev) {
+            grad = ORA_MODE_L2;
+            if (switch_iter)
+                *switch_iter = t + 1;
+        }
+        osc_prev = osc;
         ++t;
         if ((double)flips < tol * (double)np)
             break;
     }
+    free(prev);
+    free(stamp);
     return t;
 }
 

@@ -19,7 +19,10 @@ extern "C" {
 #endif
 
 enum { ORA_PC = 0, ORA_PS = 1 };
-enum { ORA_MODE_SOBOLEV = 0, ORA_MODE_L2 = 1 };
+/* AUTO: Sobolev gradients until oscillation is detected, L2-type gradients
+ * from the next iteration on (Section "Particle approximation", the remark
+ * after Eq. (6), and the Fig. 3 experiment); see ora_reversals. */
+enum { ORA_MODE_SOBOLEV = 0, ORA_MODE_L2 = 1, ORA_MODE_AUTO = 2 };
 enum { ORA_NEIGH_BRUTE = 0, ORA_NEIGH_CELLS = 1 };
 
 typedef struct {
@@ -68,11 +71,26 @@ int64_t ora_step(const ora_params* P, const double* I, int32_t* L, int32_t mode,
                  int64_t cap, int64_t* lin, int32_t* a, int32_t* b,
                  double* dE_l2, double* dE_h1, int64_t* nflips);
 
-/* Repeat ora_step until max_iters or nflips < tol * N_t.  Per-iteration N_t
- * and flips go to hist_n / hist_f (max_iters entries each, may be NULL).
- * Returns iterations done. */
+/* Oscillation test of one iteration.  A reversal is a pixel that changes
+ * label in iteration t (L_prev -> L_next differ) and also changed in
+ * iteration t - 1; stamp[x] holds 1 + the last iteration in which pixel x
+ * changed (0: never) and is updated here.  Returns the number of reversals.
+ * Reading (the paper only says oscillations are easily detected): the
+ * contour oscillates when at least half of an iteration's flips are
+ * reversals, in two iterations in a row (ora_run). */
+int64_t ora_reversals(int64_t nvox, const int32_t* L_prev, const int32_t* L_next,
+                      uint32_t* stamp, int64_t t);
+
+/* Repeat ora_step until max_iters or nflips < tol * N_t.  Per-iteration N_t,
+ * flips and reversals go to hist_n / hist_f / hist_b (max_iters entries
+ * each, may be NULL).  An iteration oscillates when flips > 0 and
+ * 2 * reversals >= flips.  In ORA_MODE_AUTO the first iteration t that
+ * oscillates right after an oscillating iteration t - 1 switches every later
+ * iteration to L2-type gradients; *switch_iter receives t + 1 (or -1: no
+ * switch; may be NULL).  Returns iterations done. */
 int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
-                int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f);
+                int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f,
+                int64_t* hist_b, int32_t* switch_iter);
 
 /* Total piecewise-constant energy: sum_x (I(x) - mu_{L(x)})^2 with region means
  * mu_l, plus lambda times the number of face-adjacent pixel pairs with

@@ -167,7 +167,7 @@ void kernel_table(double E, double eps, int T, float* W)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t lab, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
+    size_t lab, fstamp, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
         part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, ds;
     size_t total;
 };
@@ -183,6 +183,7 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
         return r;
     };
     L.lab = take((size_t)nvox * 2);
+    L.fstamp = take((size_t)nvox * 4);
     L.rec0 = take((size_t)cap * 8);
     L.rec1 = take((size_t)cap * 8);
     L.ts0 = take((size_t)(g.ntiles + 1) * 4);
@@ -198,8 +199,8 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     L.st_s1 = take((size_t)p->max_labels * 8);
     L.lstat = take((size_t)p->max_labels * 16);
     L.W = take((size_t)kMaxT * 4);
-    L.hist = take((size_t)2 * kHist * 4);
-    L.part_f = take((size_t)g.gp * 4);
+    L.hist = take((size_t)3 * kHist * 4);
+    L.part_f = take((size_t)g.gp * 8);
     L.part_n = take((size_t)g.gp * kSmallM * 8);
     L.part_q = take((size_t)g.gp * kSmallM * 8);
     L.part_cnt = take((size_t)g.ge * 4);
@@ -215,6 +216,7 @@ Bufs carve(const Layout& L, char* base, long long cap)
 {
     Bufs b{};
     b.lab = (unsigned short*)(base + L.lab);
+    b.fstamp = (unsigned*)(base + L.fstamp);
     b.rec[0] = (uint2*)(base + L.rec0);
     b.rec[1] = (uint2*)(base + L.rec1);
     b.tstart[0] = (unsigned*)(base + L.ts0);
@@ -273,8 +275,8 @@ struct sobrc_ctx {
     bool initialized = false;
     // hipGraph of two consecutive steps, per start parity and mode
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec[2][2] = {};
-    float gtol[2][2] = {};
+    hipGraphExec_t gexec[2][3] = {};  // [start parity][gradient mode]
+    float gtol[2][3] = {};
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev;   // pool, pairs
@@ -334,20 +336,24 @@ int32_t launch_step(sobrc_ctx* c, int mode, int32_t* d_nflips, float tol, hipStr
     int cur = c->cur, nxt = 1 - cur;
     const Geom& g = c->g;
     const Bufs& b = c->b;
+    // auto mode: the Sobolev kernel skips itself and the acceptance reads the
+    // L2 gradients once the device has switched (latched per step)
+    const int flags = kGate | (mode == SOBRC_MODE_AUTO ? kAuto : 0);
     SOBRC_TRY(timed(c, SOBRC_K_L2DIFF, s, "k_l2diff",
                     [&] { return launch_l2diff(g, b, c->image, cur, b.dE, 1, s); }));
     const float* grad = b.dE;
-    if (mode == SOBRC_MODE_SOBOLEV) {
+    if (mode != SOBRC_MODE_L2) {
         SOBRC_TRY(timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
-                        [&] { return launch_sobolev(g, b, c->sw, cur, b.dE, b.gH1, 1, 1, s); }));
+                        [&] { return launch_sobolev(g, b, c->sw, cur, b.dE, b.gH1, flags, 1, s); }));
         grad = b.gH1;
     }
-    SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip", [&] { return launch_flip(g, b, c->image, cur, grad, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip",
+                    [&] { return launch_flip(g, b, c->image, cur, grad, b.dE, flags, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_COUNT, s, "k_count", [&] { return launch_count(g, b, cur, 1, 0, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_SCAN, s, "k_scan",
-                    [&] { return launch_scan(g, b, cur, nxt, 0, tol, d_nflips, 1, s); }));
+                    [&] { return launch_scan(g, b, cur, nxt, 0, tol, d_nflips, flags, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_WRITE, s, "k_write",
-                    [&] { return launch_write(g, b, c->image, cur, nxt, grad, 0, s); }));
+                    [&] { return launch_write(g, b, c->image, cur, nxt, grad, b.dE, flags, 0, s); }));
     c->cur = nxt;
     return SOBRC_OK;
 }
@@ -478,6 +484,7 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
     SOBRC_HIP(hipMemsetAsync(b.st_n, 0, (size_t)c->p.max_labels * 8, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.st_s1, 0, (size_t)c->p.max_labels * 8, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.dirty, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
+    SOBRC_HIP(hipMemsetAsync(b.fstamp, 0, (size_t)g.nx * g.ny * g.nz * 4, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.part_cnt, 0, (size_t)g.ge * 4, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.part_act, 0, (size_t)g.ge * 4, s), "hipMemsetAsync");
     SOBRC_TRY(upload_tables(g, c->p.E, c->p.eps, b.W, &c->sw, s));
@@ -505,7 +512,7 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
     SOBRC_HIP(launch_stats_init(g, b, d_image, s), "k_stats_init");
     SOBRC_HIP(launch_count(g, b, 0, 0, 1, s), "k_count");
     SOBRC_HIP(launch_scan(g, b, 0, 0, 1, 0.f, nullptr, 0, s), "k_scan");
-    SOBRC_HIP(launch_write(g, b, d_image, 0, 0, nullptr, 1, s), "k_write");
+    SOBRC_HIP(launch_write(g, b, d_image, 0, 0, nullptr, nullptr, 0, 1, s), "k_write");
     SOBRC_TRY(read_state(c, &h, s));
     if (h.err & kErrCapacity)
         return fail(SOBRC_ECAPACITY, "initial particle set needs %u entries > max_particles %lld", h.need,
@@ -549,8 +556,8 @@ int32_t step(sobrc_ctx* c, int32_t mode, int32_t* d_nflips, void* stream)
         return fail(SOBRC_EINVAL, "ctx is NULL");
     if (!c->initialized)
         return fail(SOBRC_ESTATE, "step before init_labels");
-    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2)
-        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV or SOBRC_MODE_L2");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
     return launch_step(c, mode, d_nflips, 0.f, (hipStream_t)stream);
 }
 
@@ -560,8 +567,8 @@ int32_t run(sobrc_ctx* c, int32_t max_iters, double flip_tol, int32_t mode, int3
         return fail(SOBRC_EINVAL, "ctx is NULL");
     if (!c->initialized)
         return fail(SOBRC_ESTATE, "run before init_labels");
-    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2)
-        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV or SOBRC_MODE_L2");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
     if (max_iters < 0 || !(flip_tol >= 0.0))
         return fail(SOBRC_EINVAL, "max_iters must be >= 0 and flip_tol >= 0");
     hipStream_t s = (hipStream_t)stream;
@@ -581,6 +588,11 @@ int32_t run(sobrc_ctx* c, int32_t max_iters, double flip_tol, int32_t mode, int3
     for (; t < max_iters; ++t)
         SOBRC_TRY(launch_step(c, mode, nullptr, (float)flip_tol, s));
     SOBRC_TRY(read_state(c, &h, s));
+    // Steps after a tolerance stop were no-ops: the state sits at the parity
+    // of the completed iterations (after a capacity roll-back both buffers
+    // hold it).  Clear the stop so that later step() calls proceed.
+    c->cur = (int)(h.iters & 1u);
+    SOBRC_HIP(hipMemsetAsync(&c->b.ds->converged, 0, sizeof(unsigned), s), "hipMemsetAsync");
     if (h_iters_done)
         *h_iters_done = (int32_t)(h.iters - it0);
     return status_of(h);
@@ -594,6 +606,7 @@ int32_t ctx_sync(sobrc_ctx* c, void* stream)
         return fail(SOBRC_ESTATE, "ctx_sync before init_labels");
     DevState h;
     SOBRC_TRY(read_state(c, &h, (hipStream_t)stream));
+    c->cur = (int)(h.iters & 1u);
     return status_of(h);
 }
 
@@ -642,7 +655,8 @@ int32_t get_region_stats(sobrc_ctx* c, int64_t* h_count, double* h_sum, void* st
     return SOBRC_OK;
 }
 
-int32_t get_history(sobrc_ctx* c, int32_t cap, int32_t* h_n, int32_t* h_flips, int32_t* h_len, void* stream)
+int32_t get_history(sobrc_ctx* c, int32_t cap, int32_t* h_n, int32_t* h_flips, int32_t* h_reversals,
+                    int32_t* h_len, void* stream)
 {
     if (!c || !h_len || cap < 0 || (cap > 0 && (!h_n || !h_flips)))
         return fail(SOBRC_EINVAL, "bad arguments to get_history");
@@ -651,8 +665,9 @@ int32_t get_history(sobrc_ctx* c, int32_t cap, int32_t* h_n, int32_t* h_flips, i
     hipStream_t s = (hipStream_t)stream;
     DevState h;
     SOBRC_TRY(read_state(c, &h, s));
-    std::vector<unsigned> hist(2 * kHist);
-    SOBRC_HIP(hipMemcpyAsync(hist.data(), c->b.hist, 8 * (size_t)kHist, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    std::vector<unsigned> hist(3 * kHist);
+    SOBRC_HIP(hipMemcpyAsync(hist.data(), c->b.hist, 12 * (size_t)kHist, hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync");
     SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     unsigned avail = h.iters < (unsigned)kHist ? h.iters : (unsigned)kHist;
     unsigned take = (unsigned)cap < avail ? (unsigned)cap : avail;
@@ -660,8 +675,22 @@ int32_t get_history(sobrc_ctx* c, int32_t cap, int32_t* h_n, int32_t* h_flips, i
         unsigned it = h.iters - take + k;
         h_n[k] = (int32_t)hist[it % kHist];
         h_flips[k] = (int32_t)hist[kHist + it % kHist];
+        if (h_reversals)
+            h_reversals[k] = (int32_t)hist[2 * kHist + it % kHist];
     }
     *h_len = (int32_t)take;
+    return SOBRC_OK;
+}
+
+int32_t get_gradient_mode(sobrc_ctx* c, int32_t* h_switch_iter, void* stream)
+{
+    if (!c || !h_switch_iter)
+        return fail(SOBRC_EINVAL, "ctx and h_switch_iter must be non-NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "get_gradient_mode before init_labels");
+    DevState h;
+    SOBRC_TRY(read_state(c, &h, (hipStream_t)stream));
+    *h_switch_iter = h.switch_it == 0 ? -1 : (int32_t)(h.switch_it - 1);
     return SOBRC_OK;
 }
 

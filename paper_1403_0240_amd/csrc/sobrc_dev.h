@@ -91,8 +91,14 @@ struct DevState {
     unsigned converged;     // flip tolerance reached: further steps do nothing
     unsigned iters;         // steps committed
     unsigned maxbits;       // init: bit pattern of max |I| (fp32 images)
-    unsigned pad[3];
+    unsigned lmode;         // bit 0: L2 gradients in force for the running step (auto mode, latched at its
+                            // start); bit 1: the last committed step oscillated
+    unsigned switch_it;     // 1 + first iteration run with L2 gradients in auto mode, 0: none yet
 };
+
+// Step-kernel flags: stop when the context has stopped (error or tolerance);
+// auto gradient mode (Sobolev until oscillation, then L2).
+constexpr int kGate = 1, kAuto = 2;
 
 // Device pointers of one context (all carved from the caller's workspace).
 struct Bufs {
@@ -102,6 +108,7 @@ struct Bufs {
     unsigned* active[2];     // non-empty tiles, ntiles each
     unsigned* tcnt;          // per-tile particle count of the next state
     unsigned* dirty;         // epoch of the last flip within one pixel of the tile
+    unsigned* fstamp;        // per pixel: 1 + the last iteration that changed its label (0: never)
     unsigned* tslot;         // per tile: emission bitmasks from k_count for k_write
     float* dE;               // L2 gradient, capacity
     float* gH1;              // Sobolev gradient, capacity
@@ -110,7 +117,7 @@ struct Bufs {
     float4* lstat;           // per label: mean, n/(n-1) (0 if n <= 1), n/(n+1)
     float* W;                // kernel table W[d^2], T entries
     unsigned* hist;          // 2 * kHist: N_t and flips_t
-    unsigned* part_f;        // flips per k_flip block
+    unsigned* part_f;        // per k_flip block: flips [gp], then reversals [gp]
     long long* part_n;       // per label x k_flip block: pixel-count deltas (small M)
     long long* part_q;       // per label x k_flip block: intensity-sum deltas (small M)
     unsigned* part_cnt;      // particles per emission block (tiles [b*Re, (b+1)*Re))
@@ -130,12 +137,12 @@ hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur,
 hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* in,
                           float* out, int gated, int use_slots, hipStream_t s);
 hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,
-                       hipStream_t s);
+                       const float* grad_l2, int flags, hipStream_t s);
 hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, hipStream_t s);
 hipError_t launch_scan(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol,
                        int32_t* d_nflips, int gated, hipStream_t s);
 hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, int nxt,
-                        const float* grad, int all_dirty, hipStream_t s);
+                        const float* grad, const float* grad_l2, int flags, int all_dirty, hipStream_t s);
 hipError_t launch_unpack(const Geom& g, const Bufs& b, int cur, int32_t* lin, int32_t* a,
                          int32_t* bb, hipStream_t s);
 hipError_t launch_labels_out(const Geom& g, const Bufs& b, int32_t* out, hipStream_t s);

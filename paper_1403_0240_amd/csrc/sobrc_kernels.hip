@@ -595,11 +595,11 @@ __device__ __forceinline__ T wave_sum(T v)
 // offsets, check the capacity (requesting a roll-back if it is exceeded), and
 // record telemetry and the convergence test.
 __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, int nxt, int is_init, float tol,
-                                                      int32_t* d_nflips, int gated)
+                                                      int32_t* d_nflips, int gated, int flags)
 {
     __shared__ unsigned long long s_sum[kScanThreads / 64];
     __shared__ unsigned s_nz[kScanThreads / 64];
-    __shared__ unsigned s_f[kScanThreads / 64];
+    __shared__ unsigned s_f[kScanThreads / 64], s_r[kScanThreads / 64];
     DevState* ds = b.ds;
     if (gated && stopped(ds))
         return;
@@ -613,12 +613,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
         sum += b.part_cnt[i];
         nz += b.part_act[i];
     }
-    unsigned f = 0;
+    unsigned f = 0, rv = 0;
     long long dn = 0, dq = 0, n0 = 0, q0 = 0;
     const bool label_wave = g.small_m && w < g.max_labels;
     if (!is_init) {
-        for (int i = tid; i < g.gp; i += kScanThreads)
+        for (int i = tid; i < g.gp; i += kScanThreads) {
             f += b.part_f[i];
+            rv += b.part_f[g.gp + i];
+        }
         if (label_wave) {
             const long long* pn = b.part_n + (long long)w * g.gp;
             const long long* pq = b.part_q + (long long)w * g.gp;
@@ -637,8 +639,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
     unsigned nf = 0;
     if (!is_init) {
         f = wave_sum(f);
-        if (lane == 0)
+        rv = wave_sum(rv);
+        if (lane == 0) {
             s_f[w] = f;
+            s_r[w] = rv;
+        }
     }
     if (label_wave) {
         dn = wave_sum(dn);
@@ -682,9 +687,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
         s_nz[w] = inz;
     }
     __syncthreads();
+    unsigned nb = 0;  // reversals
     if (!is_init)
-        for (int i = 0; i < kScanThreads / 64; ++i)
+        for (int i = 0; i < kScanThreads / 64; ++i) {
             nf += s_f[i];
+            nb += s_r[i];
+        }
     unsigned long long off = 0, total = 0;
     unsigned offz = 0, totz = 0;
     for (int i = 0; i < kScanThreads / 64; ++i) {
@@ -734,11 +742,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
                 unsigned ncur = ds->n[cur], it = ds->iters;
                 b.hist[it % kHist] = ncur;
                 b.hist[kHist + it % kHist] = nf;
+                b.hist[2 * kHist + it % kHist] = nb;
                 ds->iters = it + 1;
                 if (d_nflips)
                     *d_nflips = (int32_t)nf;
                 if (tol > 0.f && (double)nf < (double)tol * (double)ncur)
                     ds->converged = 1;
+                // oscillation: at least half of the flips are reversals, in
+                // this step and the one before; auto mode then uses L2
+                // gradients from the next step on
+                const bool osc = nf > 0u && 2ull * nb >= (unsigned long long)nf;
+                const unsigned lm = ds->lmode;
+                if ((flags & kAuto) && ds->switch_it == 0u && osc && (lm & 2u))
+                    ds->switch_it = it + 2u;
+                ds->lmode = (lm & 1u) | (osc ? 2u : 0u);
             }
         }
     }
@@ -773,7 +790,8 @@ __device__ __forceinline__ bool decide_move(const uint2* rec, const float* grad,
 // from the labels in canonical order, clean tiles copy their records from
 // state t.  On an overflowing step, restore state t instead.
 __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* img, int cur, int nxt,
-                                                 const float* __restrict__ grad, int all_dirty)
+                                                 const float* __restrict__ grad_sob,
+                                                 const float* __restrict__ grad_l2, int flags, int all_dirty)
 {
     __shared__ WaveEmit W[kBlock / 64];
     __shared__ unsigned s_red[kBlock / 64];
@@ -783,6 +801,8 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     __shared__ unsigned s_ndl;
     DevState* ds = b.ds;
     if (ds->undo) {
+        // the same gradients k_flip decided on in this step
+        const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
         long long stride = (long long)gridDim.x * kBlock;
         unsigned n = ds->n[cur];
         for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
@@ -904,6 +924,7 @@ __global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* i
         ds->go = 0;
         ds->undo = 0;
         ds->epoch = ds->epoch + 1;
+        ds->lmode = (ds->lmode & ~1u) | (ds->switch_it != 0 ? 1u : 0u);
     }
     if (gated && stopped(ds))
         return;
@@ -1121,8 +1142,10 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_generic(Geom g, Bufs b, i
                                                               float* __restrict__ out, int gated)
 {
     extern __shared__ __align__(16) char lds[];
-    if (gated && stopped(b.ds))
+    if ((gated & kGate) && stopped(b.ds))
         return;
+    if ((gated & kAuto) && (b.ds->lmode & 1u))
+        return;  // L2 gradients in force: no smoothing
     unsigned a0, a1;
     xcd_chunk(b.ds->n_active[cur], a0, a1);
     for (unsigned ai = a0; ai < a1; ++ai)
@@ -1188,8 +1211,10 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
     float2* s_v = (float2*)lds;                   // (value of a lo->hi particle, value of a hi->lo particle)
     unsigned* s_n = (unsigned*)(s_v + S::NCELL);  // their counts, packed lo->hi | hi->lo << 16
     DevState* ds = b.ds;
-    if (gated && stopped(ds))
+    if ((gated & kGate) && stopped(ds))
         return;
+    if ((gated & kAuto) && (ds->lmode & 1u))
+        return;  // L2 gradients in force: no smoothing
     unsigned a0, a1;
     xcd_chunk(ds->n_active[cur], a0, a1);
     const unsigned* ts = b.tstart[cur];
@@ -1355,10 +1380,11 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
 // few labels, wave-merged atomics otherwise.  Tiles within one pixel of a
 // flip are marked dirty for the particle-set update.
 __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img, int cur,
-                                                const float* __restrict__ grad)
+                                                const float* __restrict__ grad_sob,
+                                                const float* __restrict__ grad_l2, int flags)
 {
     __shared__ long long s_dn[kSmallM], s_dq[kSmallM];
-    __shared__ unsigned s_f;
+    __shared__ unsigned s_f, s_rv;
     DevState* ds = b.ds;
     if (stopped(ds))
         return;
@@ -1366,11 +1392,14 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
         s_dn[threadIdx.x] = 0;
         s_dq[threadIdx.x] = 0;
     }
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         s_f = 0;
+        s_rv = 0;
+    }
     __syncthreads();
     const unsigned n = ds->n[cur];
-    const unsigned epoch = ds->epoch;
+    const unsigned epoch = ds->epoch, it = ds->iters;
+    const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
     const uint2* rec = b.rec[cur];
     const int lane = lane_id();
     const int TX = 1 << g.tsx, TY = 1 << g.tsy, TZ = 1 << g.tsz;
@@ -1378,7 +1407,7 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
     xcd_chunk(n, p0, p1);
     for (unsigned base = p0; base < p1; base += kBlock) {
         unsigned p = base + threadIdx.x;
-        bool f = false;
+        bool f = false, rev = false;
         unsigned lin = 0;
         int a = 0, bb = 0;
         if (p < p1) {
@@ -1390,6 +1419,9 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
                 lin = (unsigned)lin_of(g, x, y, z);
                 a = (int)(r.y & 0xffffu);
                 b.lab[lin] = (unsigned short)bb;
+                const unsigned st = b.fstamp[lin];
+                rev = st != 0u && st == it;  // this pixel also changed in the previous iteration
+                b.fstamp[lin] = it + 1u;
                 int tx = x >> g.tsx, ty = y >> g.tsy, tz = z >> g.tsz;
                 int lx = x & (TX - 1), ly = y & (TY - 1), lz = z & (TZ - 1);
                 int x0 = (lx == 0 && tx > 0) ? -1 : 0, x1 = (lx == TX - 1 && tx + 1 < g.ntx) ? 1 : 0;
@@ -1405,8 +1437,12 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
         if (m == 0)
             continue;
         int leader = __ffsll((long long)m) - 1;
-        if (lane == leader)
+        const unsigned long long mr = __ballot(rev);
+        if (lane == leader) {
             atomicAdd(&s_f, (unsigned)__popcll(m));
+            if (mr)
+                atomicAdd(&s_rv, (unsigned)__popcll(mr));
+        }
         long long q = f ? qvalue(g, img, lin) : 0;
         unsigned key = f ? ((unsigned)min(a, bb) | ((unsigned)max(a, bb) << 16)) : 0u;
         long long sgn = bb > a ? 1 : -1;  // +1: move from the smaller to the larger label
@@ -1436,8 +1472,10 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         b.part_f[blockIdx.x] = s_f;
+        b.part_f[gridDim.x + blockIdx.x] = s_rv;
+    }
     if (g.small_m && (int)threadIdx.x < g.max_labels) {
         b.part_n[(long long)threadIdx.x * gridDim.x + blockIdx.x] = s_dn[threadIdx.x];
         b.part_q[(long long)threadIdx.x * gridDim.x + blockIdx.x] = s_dq[threadIdx.x];
@@ -1624,9 +1662,10 @@ hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad, hipStream_t s)
+hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,
+                       const float* grad_l2, int flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_flip, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, grad);
+    hipLaunchKernelGGL(k_flip, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, grad, grad_l2, flags);
     return hipGetLastError();
 }
 
@@ -1639,14 +1678,16 @@ hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int al
 hipError_t launch_scan(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol, int32_t* d_nflips,
                        int gated, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, g, b, cur, nxt, is_init, tol, d_nflips, gated);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, g, b, cur, nxt, is_init, tol, d_nflips,
+                       gated & kGate, gated & kAuto);
     return hipGetLastError();
 }
 
 hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, int nxt, const float* grad,
-                        int all_dirty, hipStream_t s)
+                        const float* grad_l2, int flags, int all_dirty, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_write, dim3(g.ge), dim3(kBlock), 0, s, g, b, img, cur, nxt, grad, all_dirty);
+    hipLaunchKernelGGL(k_write, dim3(g.ge), dim3(kBlock), 0, s, g, b, img, cur, nxt, grad, grad_l2, flags,
+                       all_dirty);
     return hipGetLastError();
 }
 

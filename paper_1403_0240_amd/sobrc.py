@@ -17,13 +17,13 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsobrc.so
 OK, EINVAL, ECAPACITY, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 F32, U16 = 0, 1
 PC, PS = 0, 1
-MODE_SOBOLEV, MODE_L2 = 0, 1
+MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE = range(6)
 KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write")
 
 EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "compute_l2_diff",
            "sobolev_smooth", "step", "run", "ctx_sync", "get_particles", "get_labels",
-           "get_region_stats", "get_history", "sobolev_particles_workspace_size",
+           "get_region_stats", "get_history", "get_gradient_mode", "sobolev_particles_workspace_size",
            "sobolev_smooth_particles", "profile_enable", "profile_read", "last_error")
 
 
@@ -67,7 +67,8 @@ def lib():
         "get_particles": [V, P(I64), V, V, V, V],
         "get_labels": [V, V, V],
         "get_region_stats": [V, V, V, V],
-        "get_history": [V, I32, V, V, P(I32), V],
+        "get_history": [V, I32, V, V, V, P(I32), V],
+        "get_gradient_mode": [V, P(I32), V],
         "sobolev_particles_workspace_size": [P(Params), I64, P(C.c_size_t)],
         "sobolev_smooth_particles": [P(Params), I64, V, V, V, V, V, V, C.c_size_t, V],
         "profile_enable": [V, I32],
@@ -245,14 +246,26 @@ def get_region_stats(ctx: Context, stream=None):
     return n, s
 
 
-def get_history(ctx: Context, cap: int = 4096, stream=None):
+def get_history(ctx: Context, cap: int = 4096, stream=None, reversals=False):
+    """(N_t, flips_t) of the most recent iterations, oldest first; with
+    reversals=True also reversals_t."""
     import numpy as np
     hn = np.zeros(cap, np.int32)
     hf = np.zeros(cap, np.int32)
+    hb = np.zeros(cap, np.int32)
     ln = C.c_int32(0)
     _check(lib().get_history(ctx.handle, cap, hn.ctypes.data_as(C.c_void_p),
-                             hf.ctypes.data_as(C.c_void_p), C.byref(ln), _stream(stream)))
-    return hn[:ln.value], hf[:ln.value]
+                             hf.ctypes.data_as(C.c_void_p), hb.ctypes.data_as(C.c_void_p),
+                             C.byref(ln), _stream(stream)))
+    k = ln.value
+    return (hn[:k], hf[:k], hb[:k]) if reversals else (hn[:k], hf[:k])
+
+
+def gradient_switch(ctx: Context, stream=None) -> int:
+    """First iteration (since init_labels) run with L2 gradients in AUTO mode, or -1."""
+    it = C.c_int32(0)
+    _check(lib().get_gradient_mode(ctx.handle, C.byref(it), _stream(stream)))
+    return it.value
 
 
 def sobolev_smooth_particles(params: Params, lin, a, b, inp, out=None, stream=None):

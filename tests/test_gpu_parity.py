@@ -177,8 +177,20 @@ def test_l2_mode_and_tolerance_stop(ora):
     assert t_g == t_o
     gn, gf = S.get_history(ctx)
     assert np.array_equal(gn, hn) and np.array_equal(gf, hf)
+    # the particle set is the one of the final labels, whatever the parity of
+    # the stopping iteration
+    lin_o, a_o, b_o = ora.particles(P, L_o)
+    lin, a, b = gpu_particles(ctx)
+    assert set(zip(lin, a, b)) == set(zip(lin_o, a_o, b_o))
     # further steps after convergence keep working (run resets the stop flag)
     assert S.run(ctx, 3, 0.0, S.MODE_L2) == 3
+    L3, _, _, _ = ora.run(P, w.image, L_o, mode=ora.MODE_L2, max_iters=3, tol=0.0)
+    if np.array_equal(S.get_labels(ctx).cpu().numpy(), L3):
+        lin3, a3, b3 = ora.particles(P, L3)
+        lin, a, b = gpu_particles(ctx)
+        assert set(zip(lin, a, b)) == set(zip(lin3, a3, b3))
+    S.step(ctx, S.MODE_L2)
+    assert S.particle_count(ctx) == len(ora.particles(P, S.get_labels(ctx).cpu().numpy())[0])
 
 
 def test_degenerate_support_equals_l2_step(ora):
@@ -352,3 +364,37 @@ def test_full_size_first_step(ora, name):
     S.step(ctx)
     nd = compare_labels(S.get_labels(ctx).cpu().numpy(), L_next, info["lin"], info["dE_h1"])
     print(f"  N={len(lin)} marginal label differences: {nd}")
+
+
+@pytest.mark.parametrize("name", ["disk2d_128", "rand3d_u16"])
+def test_auto_mode_matches_oracle(ora, name):
+    """AUTO gradient mode: same per-iteration particle counts, flips and
+    reversals as the oracle, the same switch to L2 gradients, the same stop
+    and final labels (unless the trajectories split at a marginal flip)."""
+    w = CASES[name]()
+    print(f"[case {name} auto]", flush=True)
+    P = ora.params_of(w)
+    o = ora.run_ex(P, w.image, w.labels, ora.MODE_AUTO, 200, 1e-3)
+    cap = max(4096, 2 * w.labels.size)  # at most one particle per pixel and other label
+    ctx, img, lab = gpu_state(w, cap=cap)
+    t_g = S.run(ctx, 200, 1e-3, S.MODE_AUTO)
+    L_g = S.get_labels(ctx).cpu().numpy()
+    gn, gf, gb = S.get_history(ctx, reversals=True)
+    if (L_g != o["L"]).any() or t_g != o["t"]:
+        k = next((i for i in range(min(len(gf), len(o["flips"])))
+                  if gf[i] != o["flips"][i] or gn[i] != o["n"][i]), None)
+        pytest.skip(f"trajectories split (first differing iteration {k})")
+    assert np.array_equal(gn, o["n"]) and np.array_equal(gf, o["flips"])
+    assert np.array_equal(gb, o["reversals"])
+    assert S.gradient_switch(ctx) == o["switch"] > 0
+    # step-by-step AUTO iterations (no graphs) follow the same path
+    ctx2, _, _ = gpu_state(w, cap=cap)
+    for _ in range(o["switch"] + 3):
+        S.step(ctx2, S.MODE_AUTO)
+    n2, f2, b2 = S.get_history(ctx2, reversals=True)
+    k = o["switch"] + 3
+    assert np.array_equal(f2, o["flips"][:k]) and np.array_equal(b2, o["reversals"][:k])
+    assert S.gradient_switch(ctx2) == o["switch"]
+    # a fresh init_labels clears the switch
+    S.init_labels(ctx2, img, lab)
+    assert S.gradient_switch(ctx2) == -1

@@ -390,3 +390,68 @@ def test_run_stops_at_tolerance(ora):
     L_b, _, _, _ = ora.run(P, w.image, L_a, max_iters=5)
     L_c, _, _, _ = ora.run(P, w.image, w.labels, max_iters=12)
     assert (L_b == L_c).all()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_reversals_count_consecutive_changes(ora, seed):
+    """ora_reversals against its definition written as set algebra: the
+    reversals of iteration t are the pixels in both change sets C_t and
+    C_{t-1} (C_t = {x : L_t(x) != L_{t+1}(x)}); the first iteration has none."""
+    rng = np.random.default_rng(seed)
+    nvox, T = 300, 8
+    seq = [rng.integers(0, 3, nvox).astype(np.int32)]
+    for _ in range(T):
+        nxt = seq[-1].copy()
+        # move a random subset; bias towards pixels that just changed so
+        # that reversals occur often
+        flip = rng.random(nvox) < 0.15
+        if len(seq) > 1:
+            flip |= (seq[-1] != seq[-2]) & (rng.random(nvox) < 0.5)
+        nxt[flip] = (nxt[flip] + rng.integers(1, 3, flip.sum())) % 3
+        seq.append(nxt.astype(np.int32))
+    stamp = np.zeros(nvox, np.uint32)
+    prev_change = set()
+    for t in range(T):
+        change = set(np.flatnonzero(seq[t] != seq[t + 1]).tolist())
+        got = ora.reversals(seq[t], seq[t + 1], stamp, t)
+        assert got == len(change & prev_change)
+        prev_change = change
+    # pixels that never changed keep stamp 0; the others hold 1 + last change
+    last = np.zeros(nvox, np.int64)
+    for t in range(T):
+        last[seq[t] != seq[t + 1]] = t + 1
+    assert np.array_equal(stamp.astype(np.int64), last)
+
+
+def test_auto_mode_is_sobolev_then_l2(ora):
+    """AUTO mode, checked step by step with the plain step function: until the
+    switch the iterations are Sobolev iterations, the switch comes at the first
+    pair of consecutive oscillating iterations (counted here from label
+    snapshots), and from then on the iterations are L2 iterations.  On this
+    workload the pure Sobolev flow ends in a period-2 oscillation (Eq. (6)
+    remark) and never meets the tolerance; AUTO does."""
+    w = W.disk2d()
+    P = ora.params_of(w)
+    I = w.image.astype(np.float64)
+    tol, cap = 1e-3, 200
+    sob = ora.run_ex(P, I, w.labels, ora.MODE_SOBOLEV, cap, tol)
+    assert sob["t"] == cap and sob["switch"] == -1
+    auto = ora.run_ex(P, I, w.labels, ora.MODE_AUTO, cap, tol)
+    s = auto["switch"]
+    assert 0 < s < auto["t"] < cap
+    L = w.labels.copy()
+    prev_changed = np.zeros(L.size, bool)
+    osc_prev, expect_switch = False, None
+    for t in range(auto["t"]):
+        mode = ora.MODE_SOBOLEV if expect_switch is None else ora.MODE_L2
+        L_next, info = ora.step(P, I, L, mode, want_arrays=False)
+        changed = (L_next != L).reshape(-1)
+        f, r = int(changed.sum()), int((changed & prev_changed).sum())
+        assert (info["n"], f, r) == (auto["n"][t], auto["flips"][t], auto["reversals"][t])
+        osc = f > 0 and 2 * r >= f
+        if expect_switch is None and osc and osc_prev:
+            expect_switch = t + 1
+        osc_prev, prev_changed, L = osc, changed, L_next
+    assert expect_switch == s
+    assert np.array_equal(L, auto["L"])
+    assert auto["flips"][-1] < tol * auto["n"][-1]
