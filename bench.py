@@ -105,6 +105,89 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}), flush=True)
 
 
+def batch_bench(a):
+    """The batched workload: every image advanced together by one set of
+    launches per iteration, against the same images run one after another
+    through the stand-alone path.  Both start from the seeded labels and run
+    the same iterations; the label fields must come out identical."""
+    import torch
+    from paper_1403_0240_amd import sobrc as S
+    from paper_1403_0240_amd import workloads as W
+
+    ws = W.batch2d()
+    iters = a.steps
+    ctxs = []
+    for w in ws:
+        # capacity: three times the initial contour (at least 4096 particles)
+        p0 = S.from_workload(w)
+        S.init_labels(*p0)
+        cap = max(4096, 3 * S.particle_count(p0[0]))
+        del p0
+        ctx, img, lab = S.from_workload(w, max_particles=cap)
+        S.init_labels(ctx, img, lab)
+        ctxs.append((ctx, img, lab))
+    n0 = sum(S.particle_count(c[0]) for c in ctxs)
+    # stand-alone: each image's run (graph replays), one after another
+    for c in ctxs[:2]:
+        S.run(c[0], a.warmup, 0.0, S.MODE_SOBOLEV)
+    solo_ms, solo_upd, solo_labels = 0.0, 0, []
+    for ctx, img, lab in ctxs:
+        S.init_labels(ctx, img, lab)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.run(ctx, iters, 0.0, S.MODE_SOBOLEV)
+        torch.cuda.synchronize()
+        solo_ms += (time.perf_counter() - t0) * 1e3
+        hn, _ = S.get_history(ctx, cap=iters)
+        solo_upd += int(hn.astype(np.int64).sum())
+        solo_labels.append(S.get_labels(ctx).cpu())
+    # batched: one batch of all images
+    B = S.Batch(len(ctxs))
+    for k, (ctx, img, lab) in enumerate(ctxs):
+        S.init_labels(ctx, img, lab)
+        B.set(k, ctx)
+    shape, _ = B.autotune(S.MODE_SOBOLEV, iters_per_trial=2)  # warm-up: launch shape
+    B.run(a.warmup, 0.0, S.MODE_SOBOLEV)
+    for k, (ctx, img, lab) in enumerate(ctxs):
+        B.set(k, None)
+        S.init_labels(ctx, img, lab)
+        B.set(k, ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = B.run(iters, 0.0, S.MODE_SOBOLEV)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3
+    assert (done == iters).all()
+    upd = 0
+    same = True
+    for k, (ctx, _, _) in enumerate(ctxs):
+        hn, _ = S.get_history(ctx, cap=iters)
+        upd += int(hn.astype(np.int64).sum())
+        same = same and torch.equal(S.get_labels(ctx).cpu(), solo_labels[k])
+    B.close()
+    n = len(ws)
+    rec = {
+        "metric": "batched images/s (one set of launches per iteration for all images)",
+        "value": n / (batch_ms * 1e-3),
+        "unit": "images/s",
+        "n_gpus": 1, "steps": iters, "warmup": a.warmup,
+        "ms_per_step": batch_ms / iters,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch2d_64", "images": n,
+                   "sides": [int(min(min(w.image.shape) for w in ws)),
+                             int(max(max(w.image.shape) for w in ws))],
+                   "E": ws[0].E, "lambda": ws[0].lam, "particles_init": n0},
+        "updates_per_s": upd / (batch_ms * 1e-3),
+        "standalone": {"images_per_s": n / (solo_ms * 1e-3), "ms_total": solo_ms,
+                       "updates_per_s": solo_upd / (solo_ms * 1e-3)},
+        "speedup_vs_standalone": solo_ms / batch_ms,
+        "launch_shape": {"part_chunk": shape[0], "lg_range": shape[1], "sob_tiles": shape[2]},
+        "labels_identical_to_standalone": bool(same and upd == solo_upd),
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +226,12 @@ def main():
     a = parse()
     if a.copy_probe:
         copy_probe()
+        return
+    if a.workload == "batch2d_64":
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        batch_bench(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "

@@ -169,6 +169,61 @@ int32_t get_history(sobrc_ctx* ctx, int32_t cap, int32_t* h_n, int32_t* h_flips,
  * init_labels across step and run calls. */
 int32_t get_gradient_mode(sobrc_ctx* ctx, int32_t* h_switch_iter, void* stream);
 
+/* ---- batches: many contexts advanced by one set of launches per iteration ----
+ *
+ * A batch is a table of n_slots slots, each empty or holding one initialised
+ * context.  batch_step / batch_run advance every live slot by whole
+ * iterations with seven launches per iteration for the whole batch (a
+ * persistent grid per step kernel walks all slots' work); each context's
+ * results are bit-identical to stepping it on its own.  The contexts of one
+ * batch must share ndim, E and eps (the Sobolev kernel geometry); image
+ * sizes, models, lambda, labels and capacities may differ.  While in a batch
+ * a context accepts only read calls (get_*, compute_l2_diff, sobolev_smooth);
+ * step, run, init_labels and ctx_destroy return ESTATE.  The workspace is
+ * caller-owned device memory (256-byte aligned) that the batch borrows until
+ * batch_destroy; contexts stay owned by the caller. */
+typedef struct sobrc_batch sobrc_batch;
+
+int32_t batch_workspace_size(int32_t n_slots, size_t* bytes);
+int32_t batch_create(int32_t n_slots, void* d_workspace, size_t bytes, sobrc_batch** out);
+/* Releases the host object and frees every slot (contexts are not destroyed). */
+int32_t batch_destroy(sobrc_batch* batch);
+
+/* Put an initialised context into `slot` (ctx != NULL) or empty the slot
+ * (ctx == NULL); a context already in the slot leaves it.  Synchronises
+ * `stream`.  EINVAL: slot out of range, or a context whose ndim / E / eps
+ * differ from the batch's; ESTATE: context not initialised or in another
+ * slot. */
+int32_t batch_set(sobrc_batch* batch, int32_t slot, sobrc_ctx* ctx, void* stream);
+
+/* One iteration of every live slot (as step() on each).  Asynchronous. */
+int32_t batch_step(sobrc_batch* batch, int32_t mode, void* stream);
+
+/* Up to max_iters iterations of every live slot; each slot stops on its own
+ * tolerance (as run() on each) while the others go on.  Synchronises at the
+ * end; h_iters_done (n_slots entries, may be NULL) receives each slot's
+ * iterations (0 for empty slots).  Returns the first error status of a
+ * slot, else SOBRC_OK. */
+int32_t batch_run(sobrc_batch* batch, int32_t max_iters, double flip_tol, int32_t mode,
+                  int32_t* h_iters_done, void* stream);
+
+/* Launch shape of the batch's slots: particles per block-item of the
+ * particle kernels (part_chunk), log2 of the tiles per emission range
+ * (lg_range, <= 8) and tiles per Sobolev block-item (sob_tiles); 0 keeps each
+ * context's own stand-alone value.  Shapes only regroup the work -- integer
+ * partial sums, the tile-major particle order and every tile's Sobolev sums
+ * are unchanged -- so results do not depend on them.  Synchronises. */
+int32_t batch_set_shape(sobrc_batch* batch, int32_t part_chunk, int32_t lg_range,
+                        int32_t sob_tiles, void* stream);
+
+/* Autotuner: runs every live slot through a fixed list of launch shapes,
+ * iters_per_trial + 1 iterations each (the real iterations of the run, which
+ * the shape does not affect), times each trial with HIP events and keeps the
+ * fastest shape.  h_shape (3 entries, may be NULL) receives it,
+ * *h_iters_done (may be NULL) the iterations run.  Synchronises. */
+int32_t batch_autotune(sobrc_batch* batch, int32_t mode, int32_t iters_per_trial,
+                       int32_t* h_shape, int32_t* h_iters_done, void* stream);
+
 /* Stateless Eq. (6) on caller-given particles (any order, n >= 0): positions
  * as linear indices d_lin, labels d_a != d_b in [0, max_labels), values d_in;
  * writes d_out in the input order.  Needs a device workspace of

@@ -284,6 +284,29 @@ struct sobrc_ctx {
     size_t ev_used = 0;           // pairs in use
     double prof_ms[SOBRC_K_NKINDS] = {};
     long long prof_n[SOBRC_K_NKINDS] = {};
+    // batch membership: while in a batch the batch owns the parity
+    sobrc_batch* batch = nullptr;
+};
+
+struct sobrc_batch {
+    int nslot = 0;
+    char* ws = nullptr;          // device tables: descriptors, parities, item offsets
+    ImgDesc* d_desc = nullptr;
+    unsigned* d_par = nullptr;
+    unsigned* d_off = nullptr;
+    std::vector<sobrc_ctx*> slot;
+    std::vector<unsigned> off;   // host copy, kNumPh rows of nslot + 1
+    unsigned totals[kNumPh] = {};
+    bool has_class = false;      // kernel geometry shared by every slot
+    Geom g0{};
+    SobW sw{};
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[3] = {};  // per gradient mode: two batched steps
+    float gtol[3] = {};
+    // launch shape of the slots (0: each context's own): particles per item
+    // of the particle kernels, log2 tiles per emission range, tiles per
+    // Sobolev item.  None of them changes any result.
+    int part_chunk = 0, lg_range = 0, sob_tiles = 0;
 };
 
 namespace {
@@ -458,6 +481,8 @@ int32_t ctx_destroy(sobrc_ctx* ctx)
 {
     if (!ctx)
         return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (ctx->batch)
+        return fail(SOBRC_ESTATE, "context is in a batch: remove it (batch_set) first");
     for (hipEvent_t e : ctx->ev)
         (void)hipEventDestroy(e);
     drop_graphs(ctx);
@@ -471,6 +496,8 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
 {
     if (!c)
         return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (c->batch)
+        return fail(SOBRC_ESTATE, "context is in a batch: remove it (batch_set) first");
     if (!d_image || !d_labels)
         return fail(SOBRC_EINVAL, "image and labels must be device pointers");
     hipStream_t s = (hipStream_t)stream;
@@ -556,6 +583,8 @@ int32_t step(sobrc_ctx* c, int32_t mode, int32_t* d_nflips, void* stream)
         return fail(SOBRC_EINVAL, "ctx is NULL");
     if (!c->initialized)
         return fail(SOBRC_ESTATE, "step before init_labels");
+    if (c->batch)
+        return fail(SOBRC_ESTATE, "context is in a batch: step the batch");
     if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
         return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
     return launch_step(c, mode, d_nflips, 0.f, (hipStream_t)stream);
@@ -567,6 +596,8 @@ int32_t run(sobrc_ctx* c, int32_t max_iters, double flip_tol, int32_t mode, int3
         return fail(SOBRC_EINVAL, "ctx is NULL");
     if (!c->initialized)
         return fail(SOBRC_ESTATE, "run before init_labels");
+    if (c->batch)
+        return fail(SOBRC_ESTATE, "context is in a batch: run the batch");
     if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
         return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
     if (max_iters < 0 || !(flip_tol >= 0.0))
@@ -691,6 +722,413 @@ int32_t get_gradient_mode(sobrc_ctx* c, int32_t* h_switch_iter, void* stream)
     DevState h;
     SOBRC_TRY(read_state(c, &h, (hipStream_t)stream));
     *h_switch_iter = h.switch_it == 0 ? -1 : (int32_t)(h.switch_it - 1);
+    return SOBRC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+struct BLayout {
+    size_t desc, par, off, total;
+};
+
+BLayout batch_layout(int nslot)
+{
+    BLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    L.desc = take(sizeof(ImgDesc) * (size_t)nslot);
+    L.par = take(4 * (size_t)nslot);
+    L.off = take(4 * (size_t)kNumPh * (size_t)(nslot + 1));
+    L.total = o;
+    return L;
+}
+
+// A slot's geometry under the batch's launch shape.  Only block counts
+// change, and only downwards, so every per-block buffer of the context's
+// workspace still fits: gp (particle kernels) <= the context's, ranges of at
+// most kBlock tiles no smaller than the context's (ge <= the context's), any
+// Sobolev block count.
+Geom slot_geom(const sobrc_batch* B, const sobrc_ctx* c)
+{
+    Geom g = c->g;
+    if (B->part_chunk > 0) {
+        long long gp = ((long long)c->p.max_particles + B->part_chunk - 1) / B->part_chunk;
+        gp = gp < 8 ? gp : (gp + 7) / 8 * 8;
+        if (gp < 1)
+            gp = 1;
+        if (gp < g.gp)
+            g.gp = (int)gp;
+    }
+    if (B->lg_range > g.lgRe) {
+        int lg = B->lg_range;
+        while ((1 << lg) > kBlock)
+            --lg;
+        g.lgRe = lg;
+        g.Re = 1 << lg;
+        g.ge = (g.ntiles + g.Re - 1) >> lg;
+    }
+    if (B->sob_tiles > 0) {
+        int sg = (g.ntiles + B->sob_tiles - 1) / B->sob_tiles;
+        sg = (sg + 7) / 8 * 8;
+        if (sg < g.sob_grid)
+            g.sob_grid = sg;
+    }
+    return g;
+}
+
+// Item offsets of every phase from the slots' launch sizes.
+void batch_offsets(sobrc_batch* B)
+{
+    const int n = B->nslot;
+    B->off.assign((size_t)kNumPh * (n + 1), 0u);
+    for (int ph = 0; ph < kNumPh; ++ph) {
+        unsigned* o = B->off.data() + (size_t)ph * (n + 1);
+        for (int i = 0; i < n; ++i) {
+            const sobrc_ctx* c = B->slot[i];
+            unsigned items = 0;
+            if (c) {
+                const Geom g = slot_geom(B, c);
+                items = ph == kPhPart ? (unsigned)g.gp
+                        : ph == kPhEmit ? (unsigned)g.ge
+                        : ph == kPhSob  ? (unsigned)g.sob_grid
+                                        : 1u;
+            }
+            unsigned end = o[i] + items;
+            o[i + 1] = ph == kPhScan ? end : (end + 7u) / 8u * 8u;
+        }
+        B->totals[ph] = o[n];
+    }
+}
+
+void batch_drop_graphs(sobrc_batch* B)
+{
+    for (auto& e : B->gexec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+}
+
+int32_t batch_launch(sobrc_batch* B, int mode, float tol, hipStream_t s)
+{
+    BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+    const int l2 = mode == SOBRC_MODE_L2;
+    const int flags = kGate | (mode == SOBRC_MODE_AUTO ? kAuto : 0);
+    SOBRC_HIP(launch_batch_step(t, B->totals, B->g0, B->sw, l2, flags, tol, s), "batched step");
+    return SOBRC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t batch_workspace_size(int32_t n_slots, size_t* bytes)
+{
+    if (n_slots < 1 || n_slots > 65536 || !bytes)
+        return fail(SOBRC_EINVAL, "n_slots must be in [1, 65536] and bytes non-NULL");
+    *bytes = batch_layout(n_slots).total;
+    return SOBRC_OK;
+}
+
+int32_t batch_create(int32_t n_slots, void* d_workspace, size_t bytes, sobrc_batch** out)
+{
+    if (!out)
+        return fail(SOBRC_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    SOBRC_TRY(batch_workspace_size(n_slots, &need));
+    if (!d_workspace || ((uintptr_t)d_workspace & 255u) != 0)
+        return fail(SOBRC_EINVAL, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < need)
+        return fail(SOBRC_EINVAL, "workspace too small: %zu < %zu bytes", bytes, need);
+    BLayout L = batch_layout(n_slots);
+    sobrc_batch* B = new (std::nothrow) sobrc_batch;
+    if (!B)
+        return fail(SOBRC_EINVAL, "out of host memory");
+    B->nslot = n_slots;
+    B->ws = (char*)d_workspace;
+    B->d_desc = (ImgDesc*)(B->ws + L.desc);
+    B->d_par = (unsigned*)(B->ws + L.par);
+    B->d_off = (unsigned*)(B->ws + L.off);
+    B->slot.assign((size_t)n_slots, nullptr);
+    batch_offsets(B);
+    std::vector<ImgDesc> empty((size_t)n_slots);
+    memset(empty.data(), 0, empty.size() * sizeof(ImgDesc));
+    hipError_t e = hipMemcpy(B->d_desc, empty.data(), empty.size() * sizeof(ImgDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(B->d_off, B->off.data(), B->off.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete B;
+        return dev_fail(e, "hipMemcpy");
+    }
+    *out = B;
+    return SOBRC_OK;
+}
+
+int32_t batch_destroy(sobrc_batch* B)
+{
+    if (!B)
+        return fail(SOBRC_EINVAL, "batch is NULL");
+    for (sobrc_ctx* c : B->slot)
+        if (c)
+            c->batch = nullptr;
+    batch_drop_graphs(B);
+    if (B->cap_stream)
+        (void)hipStreamDestroy(B->cap_stream);
+    delete B;
+    return SOBRC_OK;
+}
+
+int32_t batch_set(sobrc_batch* B, int32_t slot, sobrc_ctx* c, void* stream)
+{
+    if (!B)
+        return fail(SOBRC_EINVAL, "batch is NULL");
+    if (slot < 0 || slot >= B->nslot)
+        return fail(SOBRC_EINVAL, "slot %d outside [0, %d)", slot, B->nslot);
+    hipStream_t s = (hipStream_t)stream;
+    if (c) {
+        if (!c->initialized)
+            return fail(SOBRC_ESTATE, "context not initialised");
+        if (c->batch && (c->batch != B || B->slot[slot] != c))
+            return fail(SOBRC_ESTATE, "context is already in a batch slot");
+        bool any = false;
+        for (sobrc_ctx* o : B->slot)
+            any = any || (o && o != B->slot[slot]);
+        if (any || B->has_class) {
+            const Geom& a = B->g0;
+            const Geom& g = c->g;
+            if (a.ndim != g.ndim || a.T != g.T || a.h != g.h || a.brick != g.brick || a.full != g.full ||
+                a.sob_lds != g.sob_lds || memcmp(&B->sw, &c->sw, sizeof(SobW)) != 0)
+                return fail(SOBRC_EINVAL, "batch slots must share ndim, E and eps");
+        }
+    }
+    // leaving context: its host parity follows the device
+    if (sobrc_ctx* o = B->slot[slot]) {
+        DevState h;
+        SOBRC_TRY(read_state(o, &h, s));
+        o->cur = (int)(h.iters & 1u);
+        o->batch = nullptr;
+        B->slot[slot] = nullptr;
+    }
+    ImgDesc d;
+    memset(&d, 0, sizeof d);
+    if (c) {
+        d.g = slot_geom(B, c);
+        d.b = c->b;
+        d.img = c->image;
+        d.live = 1;
+        if (!B->has_class) {
+            B->g0 = c->g;
+            B->sw = c->sw;
+            B->has_class = true;
+        }
+        c->batch = B;
+        B->slot[slot] = c;
+    }
+    batch_offsets(B);
+    const unsigned par = c ? (unsigned)c->cur : 0u;
+    SOBRC_HIP(hipMemcpyAsync(B->d_desc + slot, &d, sizeof d, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipMemcpyAsync(B->d_par + slot, &par, 4, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    SOBRC_HIP(hipMemcpyAsync(B->d_off, B->off.data(), B->off.size() * 4, hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync");
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");  // host copies above are on the stack
+    return SOBRC_OK;
+}
+
+int32_t batch_step(sobrc_batch* B, int32_t mode, void* stream)
+{
+    if (!B)
+        return fail(SOBRC_EINVAL, "batch is NULL");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
+    if (!B->has_class)
+        return SOBRC_OK;
+    SOBRC_TRY(batch_launch(B, mode, 0.f, (hipStream_t)stream));
+    for (sobrc_ctx* c : B->slot)
+        if (c)
+            c->cur ^= 1;  // as step(): the device may have stopped; batch_run / batch_set re-derive it
+    return SOBRC_OK;
+}
+
+int32_t batch_run(sobrc_batch* B, int32_t max_iters, double flip_tol, int32_t mode, int32_t* h_iters_done,
+                  void* stream)
+{
+    if (!B)
+        return fail(SOBRC_EINVAL, "batch is NULL");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
+    if (max_iters < 0 || !(flip_tol >= 0.0))
+        return fail(SOBRC_EINVAL, "max_iters must be >= 0 and flip_tol >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = B->nslot;
+    std::vector<unsigned> it0((size_t)n, 0u);
+    for (int i = 0; i < n; ++i)
+        if (sobrc_ctx* c = B->slot[i]) {
+            DevState h;
+            SOBRC_TRY(read_state(c, &h, s));
+            SOBRC_TRY(status_of(h));
+            it0[i] = h.iters;
+        }
+    if (B->has_class && max_iters > 0) {
+        BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+        SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
+        int k = 0;
+        if (max_iters >= 2) {
+            hipGraphExec_t& e = B->gexec[mode];
+            if (e && B->gtol[mode] != (float)flip_tol) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+            if (!e) {
+                if (!B->cap_stream)
+                    SOBRC_HIP(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+                hipGraph_t graph = nullptr;
+                SOBRC_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal),
+                          "hipStreamBeginCapture");
+                int32_t r1 = batch_launch(B, mode, (float)flip_tol, B->cap_stream);
+                int32_t r2 = r1 == SOBRC_OK ? batch_launch(B, mode, (float)flip_tol, B->cap_stream) : r1;
+                hipError_t ec = hipStreamEndCapture(B->cap_stream, &graph);
+                if (r2 != SOBRC_OK) {
+                    if (graph)
+                        (void)hipGraphDestroy(graph);
+                    return r2;
+                }
+                if (ec != hipSuccess)
+                    return dev_fail(ec, "hipStreamEndCapture");
+                hipError_t ei = hipGraphInstantiate(&e, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ei != hipSuccess) {
+                    e = nullptr;
+                    return dev_fail(ei, "hipGraphInstantiate");
+                }
+                B->gtol[mode] = (float)flip_tol;
+            }
+            for (; k + 2 <= max_iters; k += 2)
+                SOBRC_HIP(hipGraphLaunch(e, s), "hipGraphLaunch");
+        }
+        for (; k < max_iters; ++k)
+            SOBRC_TRY(batch_launch(B, mode, (float)flip_tol, s));
+    }
+    int32_t status = SOBRC_OK;
+    for (int i = 0; i < n; ++i) {
+        if (h_iters_done)
+            h_iters_done[i] = 0;
+        if (sobrc_ctx* c = B->slot[i]) {
+            DevState h;
+            SOBRC_TRY(read_state(c, &h, s));
+            c->cur = (int)(h.iters & 1u);
+            if (h_iters_done)
+                h_iters_done[i] = (int32_t)(h.iters - it0[i]);
+            if (status == SOBRC_OK)
+                status = status_of(h);
+        }
+    }
+    if (B->has_class) {
+        BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+        SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
+    }
+    return status;
+}
+
+int32_t batch_set_shape(sobrc_batch* B, int32_t part_chunk, int32_t lg_range, int32_t sob_tiles, void* stream)
+{
+    if (!B)
+        return fail(SOBRC_EINVAL, "batch is NULL");
+    if (part_chunk < 0 || lg_range < 0 || lg_range > 8 || sob_tiles < 0)
+        return fail(SOBRC_EINVAL, "bad launch shape");
+    hipStream_t s = (hipStream_t)stream;
+    B->part_chunk = part_chunk;
+    B->lg_range = lg_range;
+    B->sob_tiles = sob_tiles;
+    batch_offsets(B);
+    std::vector<ImgDesc> d((size_t)B->nslot);
+    memset(d.data(), 0, d.size() * sizeof(ImgDesc));
+    for (int i = 0; i < B->nslot; ++i)
+        if (sobrc_ctx* c = B->slot[i]) {
+            d[i].g = slot_geom(B, c);
+            d[i].b = c->b;
+            d[i].img = c->image;
+            d[i].live = 1;
+        }
+    SOBRC_HIP(hipMemcpyAsync(B->d_desc, d.data(), d.size() * sizeof(ImgDesc), hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync");
+    SOBRC_HIP(hipMemcpyAsync(B->d_off, B->off.data(), B->off.size() * 4, hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync");
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    batch_drop_graphs(B);  // grid sizes follow the item counts
+    return SOBRC_OK;
+}
+
+int32_t batch_autotune(sobrc_batch* B, int32_t mode, int32_t iters_per_trial, int32_t* h_shape,
+                       int32_t* h_iters_done, void* stream)
+{
+    if (!B || iters_per_trial < 1)
+        return fail(SOBRC_EINVAL, "batch is NULL or iters_per_trial < 1");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
+    hipStream_t s = (hipStream_t)stream;
+    // candidates: the contexts' own shape, then coarser items
+    const int cand[][3] = {{0, 0, 0},     {1024, 3, 4},  {1024, 5, 8},  {2048, 5, 16}, {4096, 6, 16},
+                           {4096, 7, 32}, {8192, 7, 64}, {2048, 4, 8},  {8192, 8, 32}};
+    const int ncand = (int)(sizeof cand / sizeof cand[0]);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SOBRC_HIP(hipEventCreate(&e0), "hipEventCreate");
+    SOBRC_HIP(hipEventCreate(&e1), "hipEventCreate");
+    int best = 0, done = 0;
+    float best_ms = 0.f;
+    int32_t rc = SOBRC_OK;
+    for (int k = 0; k < ncand && rc == SOBRC_OK; ++k) {
+        rc = batch_set_shape(B, cand[k][0], cand[k][1], cand[k][2], stream);
+        if (rc != SOBRC_OK)
+            break;
+        // one untimed iteration settles the new shape, then the timed trial
+        rc = batch_launch(B, mode, 0.f, s);
+        for (int t = 0; t < iters_per_trial && rc == SOBRC_OK; ++t) {
+            if (t == 0 && hipEventRecord(e0, s) != hipSuccess)
+                rc = fail(SOBRC_EDEVICE, "hipEventRecord");
+            if (rc == SOBRC_OK)
+                rc = batch_launch(B, mode, 0.f, s);
+        }
+        if (rc != SOBRC_OK)
+            break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(SOBRC_EDEVICE, "event timing");
+            break;
+        }
+        done += iters_per_trial + 1;
+        if (k == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SOBRC_OK)
+        return rc;
+    SOBRC_TRY(batch_set_shape(B, cand[best][0], cand[best][1], cand[best][2], stream));
+    for (int i = 0; i < B->nslot; ++i)
+        if (sobrc_ctx* c = B->slot[i]) {
+            DevState h;
+            SOBRC_TRY(read_state(c, &h, s));
+            c->cur = (int)(h.iters & 1u);
+        }
+    if (h_shape) {
+        h_shape[0] = cand[best][0];
+        h_shape[1] = cand[best][1];
+        h_shape[2] = cand[best][2];
+    }
+    if (h_iters_done)
+        *h_iters_done = done;
     return SOBRC_OK;
 }
 

@@ -96,6 +96,13 @@ struct DevState {
     unsigned switch_it;     // 1 + first iteration run with L2 gradients in auto mode, 0: none yet
 };
 
+// A block's place in the work of one context: its index and the block count
+// of that context's launch.  Stand-alone launches use the hardware block
+// index; batched launches map their blocks onto the contexts of the batch.
+struct VB {
+    unsigned id, n;
+};
+
 // Step-kernel flags: stop when the context has stopped (error or tolerance);
 // auto gradient mode (Sobolev until oscillation, then L2).
 constexpr int kGate = 1, kAuto = 2;
@@ -128,6 +135,31 @@ struct Bufs {
     unsigned cap;
 };
 
+// One slot of a batch (device memory): the context's geometry, buffers and
+// image; live = 0 marks an empty slot.
+struct ImgDesc {
+    Geom g;
+    Bufs b;
+    const void* img;
+    unsigned live;
+    unsigned pad;
+};
+
+// Item spaces of a batched step: per slot, the blocks the context would
+// launch on its own -- particle kernels (gp), emission kernels (ge), the
+// Sobolev kernel (sob_grid), one scan block.  Each slot's range starts at a
+// multiple of 8 so that item & 7 names the XCD as in a stand-alone launch.
+enum { kPhPart = 0, kPhEmit = 1, kPhSob = 2, kPhScan = 3, kNumPh = 4 };
+constexpr int kPersist = 2048;  // blocks of a persistent batched launch
+
+struct BatchTab {
+    const ImgDesc* d;     // nslot descriptors
+    unsigned* par;        // per slot: parity of the current state buffer
+    const unsigned* off;  // kNumPh rows of nslot + 1 item offsets
+    int nslot;
+};
+
+
 // Host wrappers around kernel launches (defined in sobrc_kernels.hip).
 hipError_t launch_init_labels(const Geom& g, const Bufs& b, const int32_t* labels_in,
                               const void* img, hipStream_t s);
@@ -143,6 +175,12 @@ hipError_t launch_scan(const Geom& g, const Bufs& b, int cur, int nxt, int is_in
                        int32_t* d_nflips, int gated, hipStream_t s);
 hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, int nxt,
                         const float* grad, const float* grad_l2, int flags, int all_dirty, hipStream_t s);
+// One batched iteration: every live slot advances by one step (seven
+// launches: gradient, Sobolev, acceptance, count, scan, write, parity).
+// totals: item counts per phase (host copy of the offsets' last entries).
+hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Geom& g0, const SobW& sw,
+                             int l2, int flags, float tol, hipStream_t s);
+hipError_t launch_batch_clear(const BatchTab& t, hipStream_t s);
 hipError_t launch_unpack(const Geom& g, const Bufs& b, int cur, int32_t* lin, int32_t* a,
                          int32_t* bb, hipStream_t s);
 hipError_t launch_labels_out(const Geom& g, const Bufs& b, int32_t* out, hipStream_t s);

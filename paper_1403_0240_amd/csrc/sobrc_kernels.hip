@@ -540,7 +540,7 @@ __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned e
 
 // Particle count of every tile of the next state, accumulated per range.
 // Clean tiles keep their previous count.
-__global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int gated, int all_dirty)
+__device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, VB vb)
 {
     __shared__ WaveEmit W[kBlock / 64];
     __shared__ unsigned s_dl[kBlock];
@@ -548,11 +548,11 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
     if (gated && stopped(b.ds))
         return;
     const unsigned epoch = b.ds->epoch;
-    const unsigned G = gridDim.x;
+    const unsigned G = vb.n;
     if (threadIdx.x == 0)
         s_ndl = 0;
     __syncthreads();
-    const unsigned j = blockIdx.x + threadIdx.x * G;  // G * kBlock >= 8 * ceil(ntiles / 8)
+    const unsigned j = vb.id + threadIdx.x * G;  // G * kBlock >= 8 * ceil(ntiles / 8)
     unsigned t;
     if (slot_tile(g, j, t)) {
         if (tile_dirty(b, t, epoch, all_dirty)) {
@@ -582,6 +582,11 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int gated, int all_dirty)
+{
+    count_body(g, b, cur, gated, all_dirty, VB{blockIdx.x, gridDim.x});
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -594,8 +599,7 @@ __device__ __forceinline__ T wave_sum(T v)
 // per-label table of the L2 gradient, scan the emission partials into block
 // offsets, check the capacity (requesting a roll-back if it is exceeded), and
 // record telemetry and the convergence test.
-__global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, int nxt, int is_init, float tol,
-                                                      int32_t* d_nflips, int gated, int flags)
+__device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol, int32_t* d_nflips, int gated, int flags, VB vb)
 {
     __shared__ unsigned long long s_sum[kScanThreads / 64];
     __shared__ unsigned s_nz[kScanThreads / 64];
@@ -761,6 +765,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, 
     }
 }
 
+__global__ __launch_bounds__(kScanThreads) void k_scan(Geom g, Bufs b, int cur, int nxt, int is_init, float tol,
+                                                      int32_t* d_nflips, int gated, int flags)
+{
+    scan_body(g, b, cur, nxt, is_init, tol, d_nflips, gated, flags, VB{blockIdx.x, gridDim.x});
+}
+
 // Per-pixel move decision of state t (shared by k_flip and the roll-back):
 // particle p starts its pixel's run of records; the smallest negative
 // gradient of the run wins, ties going to the first (smaller target label).
@@ -789,9 +799,7 @@ __device__ __forceinline__ bool decide_move(const uint2* rec, const float* grad,
 // Write the particle records of the next state: dirty tiles are re-emitted
 // from the labels in canonical order, clean tiles copy their records from
 // state t.  On an overflowing step, restore state t instead.
-__global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* img, int cur, int nxt,
-                                                 const float* __restrict__ grad_sob,
-                                                 const float* __restrict__ grad_l2, int flags, int all_dirty)
+__device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const void* img, int cur, int nxt, const float* __restrict__ grad_sob, const float* __restrict__ grad_l2, int flags, int all_dirty, VB vb)
 {
     __shared__ WaveEmit W[kBlock / 64];
     __shared__ unsigned s_red[kBlock / 64];
@@ -803,9 +811,9 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     if (ds->undo) {
         // the same gradients k_flip decided on in this step
         const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
-        long long stride = (long long)gridDim.x * kBlock;
+        long long stride = (long long)vb.n * kBlock;
         unsigned n = ds->n[cur];
-        for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        for (long long i = (long long)vb.id * kBlock + threadIdx.x; i < n; i += stride) {
             b.rec[nxt][i] = b.rec[cur][i];
             uint2 r;
             int bb = 0;
@@ -827,9 +835,9 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     if (!ds->go)
         return;
     const unsigned epoch = ds->epoch;
-    // range blockIdx.x: offsets, non-empty tile list, and the clean tiles'
+    // range vb.id: offsets, non-empty tile list, and the clean tiles'
     // records moved unchanged to their new offsets
-    const int t0 = blockIdx.x << g.lgRe, t1 = min(t0 + g.Re, g.ntiles);
+    const int t0 = vb.id << g.lgRe, t1 = min(t0 + g.Re, g.ntiles);
     const int t = t0 + (int)threadIdx.x;
     const bool in = t < t1;
     const unsigned c = in ? b.tcnt[t] : 0;
@@ -837,7 +845,7 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     unsigned tot, totz;
     const unsigned ex = block_exscan_u(c, s_red, &tot);
     const unsigned exz = block_exscan_u(c != 0 ? 1u : 0u, s_red, &totz);
-    const unsigned base = b.part_off[blockIdx.x], abase = b.part_aoff[blockIdx.x];
+    const unsigned base = b.part_off[vb.id], abase = b.part_aoff[vb.id];
     if (in) {
         b.tstart[nxt][t] = base + ex;
         if (c)
@@ -878,8 +886,8 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
                 rec[dst[u]] = r[u];
     }
     // dirty tiles of this block's round-robin share are re-emitted from the labels
-    const unsigned G = gridDim.x;
-    const unsigned jd = blockIdx.x + threadIdx.x * G;
+    const unsigned G = vb.n;
+    const unsigned jd = vb.id + threadIdx.x * G;
     unsigned td;
     if (slot_tile(g, jd, td) && b.tcnt[td] && tile_dirty(b, td, epoch, all_dirty))
         s_dl[atomicAdd(&s_ndl, 1u)] = td;
@@ -898,14 +906,21 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* img, int cur, int nxt,
+                                                 const float* __restrict__ grad_sob,
+                                                 const float* __restrict__ grad_l2, int flags, int all_dirty)
+{
+    write_body(g, b, img, cur, nxt, grad_sob, grad_l2, flags, all_dirty, VB{blockIdx.x, gridDim.x});
+}
+
 // Items [a0, a1) of [0, na) for this block: contiguous chunks, consecutive
 // chunks on the same XCD (blocks are dealt to the 8 XCDs round-robin), so
 // that work on neighbouring tiles shares one L2.  Grids that are not a
 // multiple of 8 take chunks in block order.
-__device__ __forceinline__ void xcd_chunk(unsigned na, unsigned& a0, unsigned& a1)
+__device__ __forceinline__ void xcd_chunk(unsigned na, VB vb, unsigned& a0, unsigned& a1)
 {
-    const unsigned G = gridDim.x;
-    const unsigned L = (G & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    const unsigned G = vb.n;
+    const unsigned L = (G & 7u) ? vb.id : (vb.id & 7u) * (G >> 3) + (vb.id >> 3);
     a0 = (unsigned)((unsigned long long)L * na / G);
     a1 = (unsigned)((unsigned long long)(L + 1) * na / G);
 }
@@ -916,11 +931,10 @@ __device__ __forceinline__ void xcd_chunk(unsigned na, unsigned& a0, unsigned& a
 //   PC: n_b/(n_b+1) (v - mu_b)^2 - n_a/(n_a-1) (v - mu_a)^2   (means re-estimated)
 //   PS: (v - m_b(x))^2 - (v - m_a(x))^2, m_l = mean of label l in the ball |y-x| <= R
 //   + lambda (c_a - c_b), c_l = face neighbours with label l (contour length).
-__global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* img, int cur, float* __restrict__ out,
-                                                  int gated)
+__device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const void* img, int cur, float* __restrict__ out, int gated, VB vb)
 {
     DevState* ds = b.ds;
-    if (gated && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (gated && vb.id == 0 && threadIdx.x == 0) {
         ds->go = 0;
         ds->undo = 0;
         ds->epoch = ds->epoch + 1;
@@ -932,7 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* i
     const uint2* rec = b.rec[cur];
     long long nxy = (long long)g.nx * g.ny;
     unsigned p0, p1;
-    xcd_chunk(n, p0, p1);
+    xcd_chunk(n, vb, p0, p1);
     for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
         uint2 r = rec[p];
         int x, y, z;
@@ -992,6 +1006,12 @@ __global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* i
         }
         out[p] = dext + g.lambda * (float)(ca - cb);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* img, int cur, float* __restrict__ out,
+                                                  int gated)
+{
+    l2diff_body(g, b, img, cur, out, gated, VB{blockIdx.x, gridDim.x});
 }
 
 // ------------------------------------------------- Sobolev update, Eq. (6)
@@ -1137,9 +1157,7 @@ __device__ void sob_generic_tile(const Geom& g, const Bufs& b, int cur, const fl
     }
 }
 
-__global__ __launch_bounds__(kSobBlock) void k_sobolev_generic(Geom g, Bufs b, int cur,
-                                                              const float* __restrict__ in,
-                                                              float* __restrict__ out, int gated)
+__device__ __forceinline__ void sobolev_generic_body(const Geom& g, const Bufs& b, int cur, const float* __restrict__ in, float* __restrict__ out, int gated, VB vb)
 {
     extern __shared__ __align__(16) char lds[];
     if ((gated & kGate) && stopped(b.ds))
@@ -1147,9 +1165,16 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_generic(Geom g, Bufs b, i
     if ((gated & kAuto) && (b.ds->lmode & 1u))
         return;  // L2 gradients in force: no smoothing
     unsigned a0, a1;
-    xcd_chunk(b.ds->n_active[cur], a0, a1);
+    xcd_chunk(b.ds->n_active[cur], vb, a0, a1);
     for (unsigned ai = a0; ai < a1; ++ai)
         sob_generic_tile(g, b, cur, in, out, b.active[cur][ai], lds);
+}
+
+__global__ __launch_bounds__(kSobBlock) void k_sobolev_generic(Geom g, Bufs b, int cur,
+                                                              const float* __restrict__ in,
+                                                              float* __restrict__ out, int gated)
+{
+    sobolev_generic_body(g, b, cur, in, out, gated, VB{blockIdx.x, gridDim.x});
 }
 
 template <int ND, int H>
@@ -1197,9 +1222,7 @@ constexpr TapList<BrickShape<ND, H>::NT> make_taps()
 }
 
 template <int ND, int H, bool FULL>
-__global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, SobW sw, int cur,
-                                                            const float* __restrict__ in,
-                                                            float* __restrict__ out, int gated)
+__device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* __restrict__ in, float* __restrict__ out, int gated, VB vb)
 {
     using S = BrickShape<ND, H>;
     constexpr TapList<S::NT> taps = make_taps<ND, H>();
@@ -1216,7 +1239,7 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
     if ((gated & kAuto) && (ds->lmode & 1u))
         return;  // L2 gradients in force: no smoothing
     unsigned a0, a1;
-    xcd_chunk(ds->n_active[cur], a0, a1);
+    xcd_chunk(ds->n_active[cur], vb, a0, a1);
     const unsigned* ts = b.tstart[cur];
     const int lane = lane_id();
     for (unsigned ai = a0; ai < a1; ++ai) {
@@ -1371,6 +1394,14 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
     }
 }
 
+template <int ND, int H, bool FULL>
+__global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, SobW sw, int cur,
+                                                            const float* __restrict__ in,
+                                                            float* __restrict__ out, int gated)
+{
+    sobolev_brick_body<ND, H, FULL>(g, b, sw, cur, in, out, gated, VB{blockIdx.x, gridDim.x});
+}
+
 // ------------------------------------------------------- acceptance of moves
 //
 // Every particle with gradient < 0 is a candidate; per pixel the smallest
@@ -1379,9 +1410,7 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
 // Region statistics follow exactly (integer deltas): per-block partials for
 // few labels, wave-merged atomics otherwise.  Tiles within one pixel of a
 // flip are marked dirty for the particle-set update.
-__global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img, int cur,
-                                                const float* __restrict__ grad_sob,
-                                                const float* __restrict__ grad_l2, int flags)
+__device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const void* img, int cur, const float* __restrict__ grad_sob, const float* __restrict__ grad_l2, int flags, VB vb)
 {
     __shared__ long long s_dn[kSmallM], s_dq[kSmallM];
     __shared__ unsigned s_f, s_rv;
@@ -1404,7 +1433,7 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
     const int lane = lane_id();
     const int TX = 1 << g.tsx, TY = 1 << g.tsy, TZ = 1 << g.tsz;
     unsigned p0, p1;
-    xcd_chunk(n, p0, p1);
+    xcd_chunk(n, vb, p0, p1);
     for (unsigned base = p0; base < p1; base += kBlock) {
         unsigned p = base + threadIdx.x;
         bool f = false, rev = false;
@@ -1473,13 +1502,20 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        b.part_f[blockIdx.x] = s_f;
-        b.part_f[gridDim.x + blockIdx.x] = s_rv;
+        b.part_f[vb.id] = s_f;
+        b.part_f[vb.n + vb.id] = s_rv;
     }
     if (g.small_m && (int)threadIdx.x < g.max_labels) {
-        b.part_n[(long long)threadIdx.x * gridDim.x + blockIdx.x] = s_dn[threadIdx.x];
-        b.part_q[(long long)threadIdx.x * gridDim.x + blockIdx.x] = s_dq[threadIdx.x];
+        b.part_n[(long long)threadIdx.x * vb.n + vb.id] = s_dn[threadIdx.x];
+        b.part_q[(long long)threadIdx.x * vb.n + vb.id] = s_dq[threadIdx.x];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img, int cur,
+                                                const float* __restrict__ grad_sob,
+                                                const float* __restrict__ grad_l2, int flags)
+{
+    flip_body(g, b, img, cur, grad_sob, grad_l2, flags, VB{blockIdx.x, gridDim.x});
 }
 
 // ------------------------------------------------------------- export / io
@@ -1731,6 +1767,214 @@ hipError_t launch_unbin(const Bufs& b, long long n, const unsigned* origin, cons
 {
     (void)b;
     hipLaunchKernelGGL(k_unbin, dim3(grid_for(n, 4096)), dim3(kBlock), 0, s, n, origin, binned, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batches
+//
+// A batched launch runs the stand-alone kernel bodies for every live slot of a
+// batch: a persistent grid (a multiple of 8 blocks, at most kPersist) walks the
+// concatenated item space of the phase, and each item becomes the block
+// (index, count) that the slot's own launch would have had.  A slot's results
+// are therefore the ones of its stand-alone run, bit for bit.
+
+// Slot holding `item`: the largest i with off[i] <= item (empty slots have
+// off[i] == off[i + 1] and are skipped).
+__device__ __forceinline__ int slot_of(const unsigned* __restrict__ off, int nslot, unsigned item)
+{
+    int lo = 0, hi = nslot;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= item)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void kb_l2diff(const ImgDesc* __restrict__ d, const unsigned* __restrict__ par,
+                                                   const unsigned* __restrict__ offs, int nslot)
+{
+    const unsigned* off = offs + kPhPart * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const unsigned v = item - off[i];
+        if (v < (unsigned)D.g.gp)
+            l2diff_body(D.g, D.b, D.img, (int)par[i], D.b.dE, 1, VB{v, (unsigned)D.g.gp});
+    }
+}
+
+__global__ __launch_bounds__(kSobBlock) void kb_sobolev_generic(const ImgDesc* __restrict__ d,
+                                                               const unsigned* __restrict__ par,
+                                                               const unsigned* __restrict__ offs, int nslot,
+                                                               int gated)
+{
+    const unsigned* off = offs + kPhSob * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const unsigned v = item - off[i];
+        if (v < (unsigned)D.g.sob_grid)
+            sobolev_generic_body(D.g, D.b, (int)par[i], D.b.dE, D.b.gH1, gated, VB{v, (unsigned)D.g.sob_grid});
+        __syncthreads();
+    }
+}
+
+template <int ND, int H, bool FULL>
+__global__ __launch_bounds__(kSobBlock) void kb_sobolev_brick(const ImgDesc* __restrict__ d,
+                                                             const unsigned* __restrict__ par,
+                                                             const unsigned* __restrict__ offs, int nslot, SobW sw,
+                                                             int gated)
+{
+    const unsigned* off = offs + kPhSob * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const unsigned v = item - off[i];
+        if (v < (unsigned)D.g.sob_grid)
+            sobolev_brick_body<ND, H, FULL>(D.g, D.b, sw, (int)par[i], D.b.dE, D.b.gH1, gated,
+                                            VB{v, (unsigned)D.g.sob_grid});
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_flip(const ImgDesc* __restrict__ d, const unsigned* __restrict__ par,
+                                                 const unsigned* __restrict__ offs, int nslot, int l2, int flags)
+{
+    const unsigned* off = offs + kPhPart * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const unsigned v = item - off[i];
+        if (v < (unsigned)D.g.gp)
+            flip_body(D.g, D.b, D.img, (int)par[i], l2 ? D.b.dE : D.b.gH1, D.b.dE, flags,
+                      VB{v, (unsigned)D.g.gp});
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_count(const ImgDesc* __restrict__ d, const unsigned* __restrict__ par,
+                                                  const unsigned* __restrict__ offs, int nslot)
+{
+    const unsigned* off = offs + kPhEmit * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const unsigned v = item - off[i];
+        if (v < (unsigned)D.g.ge)
+            count_body(D.g, D.b, (int)par[i], 1, 0, VB{v, (unsigned)D.g.ge});
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void kb_scan(const ImgDesc* __restrict__ d,
+                                                       const unsigned* __restrict__ par,
+                                                       const unsigned* __restrict__ offs, int nslot, float tol,
+                                                       int flags)
+{
+    const unsigned* off = offs + kPhScan * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const int cur = (int)par[i];
+        scan_body(D.g, D.b, cur, 1 - cur, 0, tol, nullptr, 1, flags & kAuto, VB{0, 1});
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_write(const ImgDesc* __restrict__ d, const unsigned* __restrict__ par,
+                                                  const unsigned* __restrict__ offs, int nslot, int l2, int flags)
+{
+    const unsigned* off = offs + kPhEmit * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const unsigned v = item - off[i];
+        const int cur = (int)par[i];
+        if (v < (unsigned)D.g.ge)
+            write_body(D.g, D.b, D.img, cur, 1 - cur, l2 ? D.b.dE : D.b.gH1, D.b.dE, flags, 0,
+                       VB{v, (unsigned)D.g.ge});
+        __syncthreads();
+    }
+}
+
+// End of a batched step: every live slot's current state is at the parity of
+// its committed iterations (a stopped or rolled-back step leaves it).
+__global__ __launch_bounds__(kBlock) void kb_advance(const ImgDesc* __restrict__ d, unsigned* __restrict__ par,
+                                                    int nslot)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nslot; i += gridDim.x * kBlock)
+        if (d[i].live)
+            par[i] = d[i].b.ds->iters & 1u;
+}
+
+// Start of a batched run: clear every live slot's tolerance stop.
+__global__ __launch_bounds__(kBlock) void kb_clear(const ImgDesc* __restrict__ d, int nslot)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nslot; i += gridDim.x * kBlock)
+        if (d[i].live)
+            d[i].b.ds->converged = 0u;
+}
+
+namespace {
+dim3 persistent_grid(unsigned items)
+{
+    unsigned g = (items + 7u) / 8u * 8u;
+    return dim3(g < 8u ? 8u : (g > (unsigned)kPersist ? (unsigned)kPersist : g));
+}
+}  // namespace
+
+hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Geom& g0, const SobW& sw, int l2,
+                             int flags, float tol, hipStream_t s)
+{
+    const int ns = t.nslot;
+    hipLaunchKernelGGL(kb_l2diff, persistent_grid(totals[kPhPart]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns);
+    if (!l2) {
+        const dim3 gd = persistent_grid(totals[kPhSob]);
+        bool done = false;
+        if (g0.brick) {
+#define SOBRC_BRICK(ND, H)                                                                                   \
+    if (!done && g0.ndim == ND && g0.h == H) {                                                                \
+        if (g0.full)                                                                                          \
+            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, true>), gd, dim3(kSobBlock), 0, s, t.d, t.par, t.off, \
+                               ns, sw, flags);                                                                \
+        else                                                                                                  \
+            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, false>), gd, dim3(kSobBlock), 0, s, t.d, t.par,       \
+                               t.off, ns, sw, flags);                                                         \
+        done = true;                                                                                          \
+    }
+            SOBRC_BRICK(3, 1) SOBRC_BRICK(3, 2) SOBRC_BRICK(3, 3) SOBRC_BRICK(3, 4)
+            SOBRC_BRICK(2, 1) SOBRC_BRICK(2, 2) SOBRC_BRICK(2, 3) SOBRC_BRICK(2, 4)
+            SOBRC_BRICK(2, 5) SOBRC_BRICK(2, 6) SOBRC_BRICK(2, 7) SOBRC_BRICK(2, 8)
+#undef SOBRC_BRICK
+        }
+        if (!done)
+            hipLaunchKernelGGL(kb_sobolev_generic, gd, dim3(kSobBlock), g0.sob_lds, s, t.d, t.par, t.off, ns,
+                               flags);
+    }
+    hipLaunchKernelGGL(kb_flip, persistent_grid(totals[kPhPart]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
+                       flags);
+    hipLaunchKernelGGL(kb_count, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns);
+    const unsigned nsc = totals[kPhScan] < 256u ? (totals[kPhScan] ? totals[kPhScan] : 1u) : 256u;
+    hipLaunchKernelGGL(kb_scan, dim3(nsc), dim3(kScanThreads), 0, s, t.d, t.par, t.off, ns, tol, flags);
+    hipLaunchKernelGGL(kb_write, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
+                       flags);
+    hipLaunchKernelGGL(kb_advance, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, s, t.d, t.par, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_clear(const BatchTab& t, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_clear, dim3((t.nslot + kBlock - 1) / kBlock), dim3(kBlock), 0, s, t.d, t.nslot);
     return hipGetLastError();
 }
 

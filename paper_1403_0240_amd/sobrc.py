@@ -24,7 +24,9 @@ KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write
 EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "compute_l2_diff",
            "sobolev_smooth", "step", "run", "ctx_sync", "get_particles", "get_labels",
            "get_region_stats", "get_history", "get_gradient_mode", "sobolev_particles_workspace_size",
-           "sobolev_smooth_particles", "profile_enable", "profile_read", "last_error")
+           "sobolev_smooth_particles", "profile_enable", "profile_read", "batch_workspace_size",
+           "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_run",
+           "batch_set_shape", "batch_autotune", "last_error")
 
 
 class SobrcError(RuntimeError):
@@ -73,6 +75,14 @@ def lib():
         "sobolev_smooth_particles": [P(Params), I64, V, V, V, V, V, V, C.c_size_t, V],
         "profile_enable": [V, I32],
         "profile_read": [V, V, V, I32],
+        "batch_workspace_size": [I32, P(C.c_size_t)],
+        "batch_create": [I32, V, C.c_size_t, P(V)],
+        "batch_destroy": [V],
+        "batch_set": [V, I32, V, V],
+        "batch_step": [V, I32, V],
+        "batch_run": [V, I32, C.c_double, I32, V, V],
+        "batch_set_shape": [V, I32, I32, I32, V],
+        "batch_autotune": [V, I32, I32, V, V, V],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -319,3 +329,59 @@ def default_capacity(shape) -> int:
     for s in shape:
         n *= int(s)
     return int(min(max(n // 4, 4096), 0x7fffffff))
+
+
+class Batch:
+    """A table of slots, each empty or holding an initialised Context; all
+    live slots advance together, one set of launches per iteration.  Keeps a
+    reference to every context in a slot."""
+
+    def __init__(self, n_slots: int, device="cuda"):
+        nb = C.c_size_t(0)
+        _check(lib().batch_workspace_size(n_slots, C.byref(nb)))
+        self.n_slots = n_slots
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        h = C.c_void_p(0)
+        _check(lib().batch_create(n_slots, _ptr(self.workspace), nb.value, C.byref(h)))
+        self.handle = h
+        self.slots = [None] * n_slots
+
+    def set(self, slot: int, ctx: "Context | None", stream=None):
+        _check(lib().batch_set(self.handle, slot, ctx.handle if ctx is not None else None,
+                               _stream(stream)))
+        self.slots[slot] = ctx
+
+    def step(self, mode=MODE_SOBOLEV, stream=None):
+        _check(lib().batch_step(self.handle, mode, _stream(stream)))
+
+    def run(self, max_iters: int, flip_tol: float = 0.0, mode=MODE_SOBOLEV, stream=None):
+        """Iterations done per slot (numpy int32, 0 for empty slots)."""
+        import numpy as np
+        done = np.zeros(self.n_slots, np.int32)
+        _check(lib().batch_run(self.handle, max_iters, float(flip_tol), mode,
+                               done.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return done
+
+    def set_shape(self, part_chunk=0, lg_range=0, sob_tiles=0, stream=None):
+        _check(lib().batch_set_shape(self.handle, part_chunk, lg_range, sob_tiles, _stream(stream)))
+
+    def autotune(self, mode=MODE_SOBOLEV, iters_per_trial=2, stream=None):
+        """Returns (chosen shape, iterations run)."""
+        import numpy as np
+        shape = np.zeros(3, np.int32)
+        done = C.c_int32(0)
+        _check(lib().batch_autotune(self.handle, mode, iters_per_trial,
+                                    shape.ctypes.data_as(C.c_void_p), C.byref(done), _stream(stream)))
+        return tuple(int(v) for v in shape), done.value
+
+    def close(self):
+        if self.handle:
+            lib().batch_destroy(self.handle)
+            self.handle = C.c_void_p(0)
+            self.slots = [None] * self.n_slots
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

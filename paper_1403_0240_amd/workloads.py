@@ -13,6 +13,8 @@ The paper's own images (Figs. 3-10) are not available; these stand in for them:
                  experiments (Figs. 6-8).
 * ``ellipsoids3d``: 256^3 uint16 piecewise-constant volume of rotated ellipsoids
                  with Gaussian noise, shaped like the 3D confocal stack (Fig. 8).
+* ``batch2d``  : 64 independent fp32 images of 128-1024 px sides with 5-30
+                 noisy disks/ellipses each (the batched workload).
 * small random multi-label cases and straight/curved contours for the tests.
 
 Pixel (x, y[, z]) has its centre at integer coordinates; arrays are indexed
@@ -222,6 +224,38 @@ def digital_disk(n: int, radius: float, E: float, center=None) -> Workload:
     c = (n / 2.0, n / 2.0) if center is None else center
     lab = ((x - c[0]) ** 2 + (y - c[1]) ** 2 <= radius ** 2).astype(np.int32)
     return Workload(f"disk_{n}_{radius}", lab.astype(np.float32), lab, E=E, lam=0.0)
+
+def blobs2d(seed: int = 100, side_lo: int = 128, side_hi: int = 1024, E: float = 8.0,
+            lam: float = 0.18, iterations: int = 200) -> Workload:
+    """One image of the batched workload: fp32, nx and ny uniform in
+    [128, 1024], 5-30 disks or ellipses (semi-axes from 6 px up to 6 + 8% of
+    the short side, painter's order) of intensity 1.0 on background 0.0,
+    Gaussian noise sigma uniform in [0.2, 0.5].  Initial labels: the shapes
+    shrunk by 2 px.  Piecewise-constant model, E = 8."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny = (int(v) for v in rng.integers(side_lo, side_hi + 1, size=2))
+    count = int(rng.integers(5, 31))
+    sigma = float(rng.uniform(0.2, 0.5))
+    x, y = _grid2d(ny, nx)
+    truth = np.zeros((ny, nx), bool)
+    lab = np.zeros((ny, nx), dtype=np.int32)
+    amax = 6.0 + 0.08 * min(nx, ny)
+    for _ in range(count):
+        a = rng.uniform(6.0, amax)
+        b = a if rng.random() < 0.5 else rng.uniform(6.0, amax)  # disk or ellipse
+        phi = rng.uniform(0.0, np.pi)
+        cx, cy = rng.uniform(amax, nx - amax), rng.uniform(amax, ny - amax)
+        truth |= _inside_ellipse(x, y, cx, cy, a, b, phi)
+        lab[_inside_ellipse(x, y, cx, cy, a, b, phi, shrink=2.0)] = 1
+    img = truth.astype(np.float64) + rng.normal(0.0, sigma, size=(ny, nx))
+    return Workload(f"blobs2d_{seed}", img.astype(np.float32), lab, E=E, lam=lam, model=PC,
+                    iterations=iterations)
+
+
+def batch2d(n_images: int = 64, seed0: int = 100) -> list:
+    """The batched workload: n_images independent blobs2d images, seeds
+    seed0 .. seed0 + n_images - 1."""
+    return [blobs2d(seed0 + k) for k in range(n_images)]
 
 
 CONFIGS = {

@@ -102,3 +102,24 @@ def test_stateless_validation(L):
     assert L.sobolev_smooth_particles(C.byref(p), 0, None, None, None, None, None, None, 0, None) == S.OK
     fake = C.c_void_p(1 << 20)
     assert L.sobolev_smooth_particles(C.byref(p), 10, fake, fake, fake, fake, fake, fake, 16, None) == S.EINVAL
+
+
+def test_batch_validation(L):
+    """Batch entry points reject bad arguments on the host."""
+    nb = C.c_size_t(0)
+    assert L.batch_workspace_size(0, C.byref(nb)) == S.EINVAL
+    assert L.batch_workspace_size(4, None) == S.EINVAL
+    assert L.batch_workspace_size(4, C.byref(nb)) == S.OK and nb.value >= 4 * 256
+    small = C.c_size_t(0)
+    L.batch_workspace_size(1, C.byref(small))
+    assert 0 < small.value < nb.value
+    h = C.c_void_p(0)
+    assert L.batch_create(4, None, nb.value, C.byref(h)) == S.EINVAL
+    assert L.batch_create(4, C.c_void_p(0x1001), nb.value, C.byref(h)) == S.EINVAL  # misaligned
+    assert L.batch_create(4, C.c_void_p(0x10000), 16, C.byref(h)) == S.EINVAL  # too small
+    assert L.batch_create(4, C.c_void_p(0x10000), nb.value, None) == S.EINVAL
+    assert not h.value
+    for rc in (L.batch_destroy(None), L.batch_set(None, 0, None, None), L.batch_step(None, 0, None),
+               L.batch_run(None, 1, 0.0, 0, None, None)):
+        assert rc == S.EINVAL
+    assert b"batch" in L.last_error()
