@@ -188,6 +188,48 @@ def batch_bench(a):
     print(json.dumps(rec), flush=True)
 
 
+def serve_bench(a):
+    """The serving workload: a seeded Poisson stream of 2D and 3D requests
+    (mean 50 requests/s) through the continuous-batching server, each run to
+    convergence; p50/p99 arrival-to-result latency and images/s."""
+    import torch
+    from paper_1403_0240_amd import serve as SV
+    from paper_1403_0240_amd import workloads as W
+
+    reqs = W.serve_stream(a.requests, rate=50.0)
+    # warm-up: a few requests alone (library load, graph capture, allocator)
+    srv = SV.Server(hbm_budget=a.hbm_gb << 30, slots=64, tol=1e-3, max_iters=500, tick=4)
+    srv.serve(reqs[:4], realtime=False)
+    srv.close()
+    torch.cuda.synchronize()
+    srv = SV.Server(hbm_budget=a.hbm_gb << 30, slots=64, tol=1e-3, max_iters=500, tick=4)
+    done = srv.serve(reqs, realtime=True)
+    srv.close()
+    st = SV.latency_stats(done)
+    # capacity: the same requests all arriving at once
+    srv = SV.Server(hbm_budget=a.hbm_gb << 30, slots=64, tol=1e-3, max_iters=500, tick=4)
+    sat = SV.latency_stats(srv.serve(reqs, realtime=False))
+    srv.close()
+    it = np.array([r.iterations for r in done])
+    conv = sum(r.iterations < 500 for r in done)
+    rec = {
+        "metric": "served images/s + p99 (continuous batching, Poisson arrivals)",
+        "value": st["images_per_s"], "unit": "images/s", "n_gpus": 1,
+        "steps": len(done), "warmup": 4, "ms_per_step": 1e3 * st["span_s"] / max(len(done), 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serve_mix", "requests": len(done), "rate_per_s": 50.0,
+                   "mix": "80% 2D fp32 256^2-2048^2, 20% 3D uint16 64^3-192^3",
+                   "tol": 1e-3, "max_iters": 500, "hbm_budget_gb": a.hbm_gb, "slots": 64},
+        "latency": {"p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_s": st["mean_s"]},
+        "saturated": {"images_per_s": sat["images_per_s"], "p50_s": sat["p50_s"],
+                      "p99_s": sat["p99_s"], "span_s": sat["span_s"]},
+        "iterations": {"p50": float(np.percentile(it, 50)), "max": int(it.max()),
+                       "converged": conv},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +240,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-events", action="store_true",
                     help="time without per-kernel events (roofline omitted)")
+    ap.add_argument("--requests", type=int, default=120, help="serving workload: request count")
+    ap.add_argument("--hbm-gb", type=int, default=16, help="serving workload: HBM budget (GiB)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 256 MiB copy used to calibrate byte counters")
     return ap.parse_args()
@@ -226,6 +270,12 @@ def main():
     a = parse()
     if a.copy_probe:
         copy_probe()
+        return
+    if a.workload == "serve_mix":
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        serve_bench(a)
         return
     if a.workload == "batch2d_64":
         if a.gpus != 1:

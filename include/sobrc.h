@@ -166,7 +166,10 @@ int32_t get_history(sobrc_ctx* ctx, int32_t cap, int32_t* h_n, int32_t* h_flips,
  * AUTO iteration use L2-type gradients; *h_switch_iter receives that first
  * L2 iteration (counted from init_labels), or -1 while there is none.  The
  * switch lasts until the next init_labels; iterations count from
- * init_labels across step and run calls. */
+ * init_labels across step and run calls.  A run (or batch run) in mode AUTO
+ * with flip_tol > 0 also stops after two iterations in a row that both used
+ * L2 gradients and in which every flip was a reversal (a settled period-2
+ * cycle: the contour sits in a minimum at pixel resolution). */
 int32_t get_gradient_mode(sobrc_ctx* ctx, int32_t* h_switch_iter, void* stream);
 
 /* ---- batches: many contexts advanced by one set of launches per iteration ----
@@ -206,6 +209,17 @@ int32_t batch_step(sobrc_batch* batch, int32_t mode, void* stream);
  * slot, else SOBRC_OK. */
 int32_t batch_run(sobrc_batch* batch, int32_t max_iters, double flip_tol, int32_t mode,
                   int32_t* h_iters_done, void* stream);
+
+/* The two halves of batch_run, for callers that keep several batches busy at
+ * once (one stream each): batch_launch_iters enqueues `iters` iterations of
+ * every live slot (each stops on its own tolerance) without synchronising;
+ * batch_collect synchronises `stream`, writes per slot (n_slots entries each,
+ * may be NULL) the iterations committed since its init_labels and whether it
+ * is stopped (tolerance met or an error), clears the tolerance stops, and
+ * returns the first error status of a slot. */
+int32_t batch_launch_iters(sobrc_batch* batch, int32_t iters, double flip_tol, int32_t mode,
+                           void* stream);
+int32_t batch_collect(sobrc_batch* batch, int32_t* h_iters, int32_t* h_stopped, void* stream);
 
 /* Launch shape of the batch's slots: particles per block-item of the
  * particle kernels (part_chunk), log2 of the tiles per emission range

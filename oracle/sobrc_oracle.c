@@ -29,7 +29,10 @@
  *  - oscillation (AUTO mode): an iteration oscillates when at least half of
  *    its flips revert pixels that changed in the iteration before; after two
  *    oscillating iterations in a row, L2-type gradients are used from the
- *    next iteration on (ora_reversals, ora_run).
+ *    next iteration on (ora_reversals, ora_run); with a flip tolerance, two
+ *    L2 iterations in a row in which every flip is a reversal (a settled
+ *    period-2 cycle) also end the run: the contour sits in a minimum at
+ *    pixel resolution.
  *
  * parity unpinned: whole-run segmentations against the paper's figures (the
  * paper's images are not available).
@@ -411,7 +414,8 @@ int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
     int32_t grad = mode == ORA_MODE_L2 ? ORA_MODE_L2 : ORA_MODE_SOBOLEV;
     if (switch_iter)
         *switch_iter = -1;
-    int osc_prev = 0;
+    int osc_prev = 0, cycle_prev = 0;
+    int32_t first_l2 = -1; /* first iteration run with L2 gradients in AUTO mode */
     int32_t t = 0;
     while (t < max_iters) {
         int64_t flips = 0;
@@ -422,14 +426,19 @@ int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
         if (hist_f) hist_f[t] = flips;
         if (hist_b) hist_b[t] = back;
         int osc = flips > 0 && 2 * back >= flips;
+        int cycle = flips > 0 && back == flips; /* every flip undoes the previous iteration's */
+        int l2_both = first_l2 >= 0 && t - 1 >= first_l2; /* t - 1 and t ran with L2 gradients */
+        int stop_osc = mode == ORA_MODE_AUTO && tol > 0.0 && l2_both && cycle && cycle_prev;
         if (mode == ORA_MODE_AUTO && grad == ORA_MODE_SOBOLEV && osc && osc_prev) {
             grad = ORA_MODE_L2;
+            first_l2 = t + 1;
             if (switch_iter)
                 *switch_iter = t + 1;
         }
         osc_prev = osc;
+        cycle_prev = cycle;
         ++t;
-        if ((double)flips < tol * (double)np)
+        if ((double)flips < tol * (double)np || stop_osc)
             break;
     }
     free(prev);

@@ -87,7 +87,10 @@ int64_t ora_reversals(int64_t nvox, const int32_t* L_prev, const int32_t* L_next
  * 2 * reversals >= flips.  In ORA_MODE_AUTO the first iteration t that
  * oscillates right after an oscillating iteration t - 1 switches every later
  * iteration to L2-type gradients; *switch_iter receives t + 1 (or -1: no
- * switch; may be NULL).  Returns iterations done. */
+ * switch; may be NULL).  With tol > 0, an AUTO run also stops after two
+ * iterations in a row that both ran with L2 gradients and in which every
+ * flip was a reversal (flips > 0 and reversals == flips).
+ * Returns iterations done. */
 int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
                 int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f,
                 int64_t* hist_b, int32_t* switch_iter);

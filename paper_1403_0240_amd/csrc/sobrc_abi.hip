@@ -294,6 +294,7 @@ struct sobrc_batch {
     ImgDesc* d_desc = nullptr;
     unsigned* d_par = nullptr;
     unsigned* d_off = nullptr;
+    uint4* d_state = nullptr;    // gathered per-slot state words
     std::vector<sobrc_ctx*> slot;
     std::vector<unsigned> off;   // host copy, kNumPh rows of nslot + 1
     unsigned totals[kNumPh] = {};
@@ -732,7 +733,7 @@ int32_t get_gradient_mode(sobrc_ctx* c, int32_t* h_switch_iter, void* stream)
 namespace {
 
 struct BLayout {
-    size_t desc, par, off, total;
+    size_t desc, par, off, state, total;
 };
 
 BLayout batch_layout(int nslot)
@@ -747,6 +748,7 @@ BLayout batch_layout(int nslot)
     L.desc = take(sizeof(ImgDesc) * (size_t)nslot);
     L.par = take(4 * (size_t)nslot);
     L.off = take(4 * (size_t)kNumPh * (size_t)(nslot + 1));
+    L.state = take(16 * (size_t)nslot);
     L.total = o;
     return L;
 }
@@ -826,6 +828,76 @@ int32_t batch_launch(sobrc_batch* B, int mode, float tol, hipStream_t s)
     return SOBRC_OK;
 }
 
+// Per-slot state words (iterations, stop, error bits, needed capacity), one
+// gather kernel and one copy for the whole batch.  Synchronises.
+int32_t batch_states(sobrc_batch* B, std::vector<uint4>& st, hipStream_t s)
+{
+    st.assign((size_t)B->nslot, make_uint4(0u, 0u, 0u, 0u));
+    if (!B->has_class)
+        return SOBRC_OK;
+    BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+    SOBRC_HIP(launch_batch_gather(t, B->d_state, s), "kb_gather");
+    SOBRC_HIP(hipMemcpyAsync(st.data(), B->d_state, st.size() * sizeof(uint4), hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync");
+    SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return SOBRC_OK;
+}
+
+int32_t slot_status(const uint4& v)
+{
+    DevState h{};
+    h.err = v.z;
+    h.need = v.w;
+    return status_of(h);
+}
+
+// Launch `iters` iterations of every live slot (graph replays of two
+// batched steps, then single steps); clears the slots' tolerance stops first.
+int32_t batch_enqueue(sobrc_batch* B, int32_t iters, float tol, int32_t mode, hipStream_t s)
+{
+    if (!B->has_class || iters <= 0)
+        return SOBRC_OK;
+    BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+    SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
+    int k = 0;
+    if (iters >= 2) {
+        hipGraphExec_t& e = B->gexec[mode];
+        if (e && B->gtol[mode] != tol) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+        if (!e) {
+            if (!B->cap_stream)
+                SOBRC_HIP(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+            hipGraph_t graph = nullptr;
+            SOBRC_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal),
+                      "hipStreamBeginCapture");
+            int32_t r1 = batch_launch(B, mode, tol, B->cap_stream);
+            int32_t r2 = r1 == SOBRC_OK ? batch_launch(B, mode, tol, B->cap_stream) : r1;
+            hipError_t ec = hipStreamEndCapture(B->cap_stream, &graph);
+            if (r2 != SOBRC_OK) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return r2;
+            }
+            if (ec != hipSuccess)
+                return dev_fail(ec, "hipStreamEndCapture");
+            hipError_t ei = hipGraphInstantiate(&e, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                e = nullptr;
+                return dev_fail(ei, "hipGraphInstantiate");
+            }
+            B->gtol[mode] = tol;
+        }
+        for (; k + 2 <= iters; k += 2)
+            SOBRC_HIP(hipGraphLaunch(e, s), "hipGraphLaunch");
+    }
+    for (; k < iters; ++k)
+        SOBRC_TRY(batch_launch(B, mode, tol, s));
+    return SOBRC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -858,6 +930,7 @@ int32_t batch_create(int32_t n_slots, void* d_workspace, size_t bytes, sobrc_bat
     B->d_desc = (ImgDesc*)(B->ws + L.desc);
     B->d_par = (unsigned*)(B->ws + L.par);
     B->d_off = (unsigned*)(B->ws + L.off);
+    B->d_state = (uint4*)(B->ws + L.state);
     B->slot.assign((size_t)n_slots, nullptr);
     batch_offsets(B);
     std::vector<ImgDesc> empty((size_t)n_slots);
@@ -958,6 +1031,43 @@ int32_t batch_step(sobrc_batch* B, int32_t mode, void* stream)
     return SOBRC_OK;
 }
 
+int32_t batch_launch_iters(sobrc_batch* B, int32_t iters, double flip_tol, int32_t mode, void* stream)
+{
+    if (!B)
+        return fail(SOBRC_EINVAL, "batch is NULL");
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
+    if (iters < 0 || !(flip_tol >= 0.0))
+        return fail(SOBRC_EINVAL, "iters must be >= 0 and flip_tol >= 0");
+    return batch_enqueue(B, iters, (float)flip_tol, mode, (hipStream_t)stream);
+}
+
+int32_t batch_collect(sobrc_batch* B, int32_t* h_iters, int32_t* h_stopped, void* stream)
+{
+    if (!B)
+        return fail(SOBRC_EINVAL, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint4> st;
+    SOBRC_TRY(batch_states(B, st, s));
+    int32_t status = SOBRC_OK;
+    for (int i = 0; i < B->nslot; ++i) {
+        const bool live = B->slot[i] != nullptr;
+        if (live)
+            B->slot[i]->cur = (int)(st[i].x & 1u);
+        if (h_iters)
+            h_iters[i] = live ? (int32_t)st[i].x : 0;
+        if (h_stopped)
+            h_stopped[i] = live && (st[i].y || st[i].z) ? 1 : 0;
+        if (live && status == SOBRC_OK)
+            status = slot_status(st[i]);
+    }
+    if (B->has_class) {
+        BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+        SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
+    }
+    return status;
+}
+
 int32_t batch_run(sobrc_batch* B, int32_t max_iters, double flip_tol, int32_t mode, int32_t* h_iters_done,
                   void* stream)
 {
@@ -969,72 +1079,17 @@ int32_t batch_run(sobrc_batch* B, int32_t max_iters, double flip_tol, int32_t mo
         return fail(SOBRC_EINVAL, "max_iters must be >= 0 and flip_tol >= 0");
     hipStream_t s = (hipStream_t)stream;
     const int n = B->nslot;
-    std::vector<unsigned> it0((size_t)n, 0u);
+    std::vector<uint4> st0;
+    SOBRC_TRY(batch_states(B, st0, s));
     for (int i = 0; i < n; ++i)
-        if (sobrc_ctx* c = B->slot[i]) {
-            DevState h;
-            SOBRC_TRY(read_state(c, &h, s));
-            SOBRC_TRY(status_of(h));
-            it0[i] = h.iters;
-        }
-    if (B->has_class && max_iters > 0) {
-        BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
-        SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
-        int k = 0;
-        if (max_iters >= 2) {
-            hipGraphExec_t& e = B->gexec[mode];
-            if (e && B->gtol[mode] != (float)flip_tol) {
-                (void)hipGraphExecDestroy(e);
-                e = nullptr;
-            }
-            if (!e) {
-                if (!B->cap_stream)
-                    SOBRC_HIP(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
-                hipGraph_t graph = nullptr;
-                SOBRC_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal),
-                          "hipStreamBeginCapture");
-                int32_t r1 = batch_launch(B, mode, (float)flip_tol, B->cap_stream);
-                int32_t r2 = r1 == SOBRC_OK ? batch_launch(B, mode, (float)flip_tol, B->cap_stream) : r1;
-                hipError_t ec = hipStreamEndCapture(B->cap_stream, &graph);
-                if (r2 != SOBRC_OK) {
-                    if (graph)
-                        (void)hipGraphDestroy(graph);
-                    return r2;
-                }
-                if (ec != hipSuccess)
-                    return dev_fail(ec, "hipStreamEndCapture");
-                hipError_t ei = hipGraphInstantiate(&e, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                if (ei != hipSuccess) {
-                    e = nullptr;
-                    return dev_fail(ei, "hipGraphInstantiate");
-                }
-                B->gtol[mode] = (float)flip_tol;
-            }
-            for (; k + 2 <= max_iters; k += 2)
-                SOBRC_HIP(hipGraphLaunch(e, s), "hipGraphLaunch");
-        }
-        for (; k < max_iters; ++k)
-            SOBRC_TRY(batch_launch(B, mode, (float)flip_tol, s));
-    }
-    int32_t status = SOBRC_OK;
-    for (int i = 0; i < n; ++i) {
-        if (h_iters_done)
-            h_iters_done[i] = 0;
-        if (sobrc_ctx* c = B->slot[i]) {
-            DevState h;
-            SOBRC_TRY(read_state(c, &h, s));
-            c->cur = (int)(h.iters & 1u);
-            if (h_iters_done)
-                h_iters_done[i] = (int32_t)(h.iters - it0[i]);
-            if (status == SOBRC_OK)
-                status = status_of(h);
-        }
-    }
-    if (B->has_class) {
-        BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
-        SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
-    }
+        if (B->slot[i])
+            SOBRC_TRY(slot_status(st0[i]));
+    SOBRC_TRY(batch_enqueue(B, max_iters, (float)flip_tol, mode, s));
+    std::vector<int32_t> it1((size_t)n, 0);
+    int32_t status = batch_collect(B, it1.data(), nullptr, stream);
+    if (h_iters_done)
+        for (int i = 0; i < n; ++i)
+            h_iters_done[i] = B->slot[i] ? it1[i] - (int32_t)st0[i].x : 0;
     return status;
 }
 

@@ -92,7 +92,8 @@ struct DevState {
     unsigned iters;         // steps committed
     unsigned maxbits;       // init: bit pattern of max |I| (fp32 images)
     unsigned lmode;         // bit 0: L2 gradients in force for the running step (auto mode, latched at its
-                            // start); bit 1: the last committed step oscillated
+                            // start); bit 1: the last committed step oscillated (reversals >= flips / 2);
+                            // bit 2: every flip of the last committed step was a reversal
     unsigned switch_it;     // 1 + first iteration run with L2 gradients in auto mode, 0: none yet
 };
 
@@ -181,6 +182,7 @@ hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, 
 hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Geom& g0, const SobW& sw,
                              int l2, int flags, float tol, hipStream_t s);
 hipError_t launch_batch_clear(const BatchTab& t, hipStream_t s);
+hipError_t launch_batch_gather(const BatchTab& t, uint4* out, hipStream_t s);
 hipError_t launch_unpack(const Geom& g, const Bufs& b, int cur, int32_t* lin, int32_t* a,
                          int32_t* bb, hipStream_t s);
 hipError_t launch_labels_out(const Geom& g, const Bufs& b, int32_t* out, hipStream_t s);

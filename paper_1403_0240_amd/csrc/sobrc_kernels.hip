@@ -756,10 +756,15 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
                 // this step and the one before; auto mode then uses L2
                 // gradients from the next step on
                 const bool osc = nf > 0u && 2ull * nb >= (unsigned long long)nf;
-                const unsigned lm = ds->lmode;
-                if ((flags & kAuto) && ds->switch_it == 0u && osc && (lm & 2u))
+                const bool cycle = nf > 0u && nb == nf;  // every flip undoes the previous step's
+                const unsigned lm = ds->lmode, sw = ds->switch_it;
+                // this step and the one before ran with L2 gradients
+                const bool l2_both = sw != 0u && sw <= it;
+                if ((flags & kAuto) && tol > 0.f && l2_both && cycle && (lm & 4u))
+                    ds->converged = 1;  // a settled cycle under L2 too: a pixel-resolution minimum
+                if ((flags & kAuto) && sw == 0u && osc && (lm & 2u))
                     ds->switch_it = it + 2u;
-                ds->lmode = (lm & 1u) | (osc ? 2u : 0u);
+                ds->lmode = (lm & 1u) | (osc ? 2u : 0u) | (cycle ? 4u : 0u);
             }
         }
     }
@@ -1925,6 +1930,21 @@ __global__ __launch_bounds__(kBlock) void kb_clear(const ImgDesc* __restrict__ d
             d[i].b.ds->converged = 0u;
 }
 
+// Per live slot, the words a collecting host needs: committed iterations,
+// stop flag, error bits, particle count that did not fit.
+__global__ __launch_bounds__(kBlock) void kb_gather(const ImgDesc* __restrict__ d, int nslot,
+                                                   uint4* __restrict__ out)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nslot; i += gridDim.x * kBlock) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (d[i].live) {
+            const DevState* ds = d[i].b.ds;
+            v = make_uint4(ds->iters, ds->converged, ds->err, ds->need);
+        }
+        out[i] = v;
+    }
+}
+
 namespace {
 dim3 persistent_grid(unsigned items)
 {
@@ -1969,6 +1989,12 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
     hipLaunchKernelGGL(kb_write, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
                        flags);
     hipLaunchKernelGGL(kb_advance, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, s, t.d, t.par, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const BatchTab& t, uint4* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_gather, dim3((t.nslot + kBlock - 1) / kBlock), dim3(kBlock), 0, s, t.d, t.nslot, out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,222 @@
+"""Continuous-batching segmentation server on one GPU.
+
+Requests (one image each, with initial labels and method parameters) are
+admitted into the free slots of a batch as soon as a slot and HBM room are
+free, run to convergence together with whatever else is resident, and retire
+on their own: the label field goes back to the host and the slot and memory
+are reused by the next request.  Requests with different kernel geometry
+(ndim, E, eps) live in separate batches, one HIP stream each, so their work
+overlaps on the device.
+
+Every iteration runs in the library's batched kernels; this module only
+decides which context sits in which slot and when.  A request's result does
+not depend on what else is resident: a batch slot follows its context's own
+stand-alone trajectory bit for bit, and a tick never takes a job past its
+iteration cap, so each job stops exactly where `run(ctx, max_iters, tol, mode)`
+on its own would.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+import torch
+
+from . import sobrc as S
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    work: object                 # workloads.Workload
+    arrival: float               # seconds since the server's clock started
+    admitted: float = -1.0
+    done: float = -1.0
+    iterations: int = 0
+    labels: np.ndarray | None = None
+    switch_iter: int = -1
+    error: str | None = None
+    footprint: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Job:
+    def __init__(self, req: Request, ctx, img, cap):
+        self.req, self.ctx, self.img, self.cap = req, ctx, img, cap
+
+
+class _Pool:
+    """One batch (one kernel geometry) with its slots, stream and the
+    committed iterations of each resident job."""
+
+    def __init__(self, n_slots: int):
+        self.batch = S.Batch(n_slots)
+        self.stream = torch.cuda.Stream()
+        self.jobs: list[_Job | None] = [None] * n_slots
+        self.iters = np.zeros(n_slots, np.int64)
+        self.ready: list[_Job] = []  # initialised, waiting for the pool to be idle
+
+    def free_slots(self) -> int:
+        return sum(j is None for j in self.jobs)
+
+    def live(self):
+        return [(k, j) for k, j in enumerate(self.jobs) if j is not None]
+
+
+def footprint(w, capacity: int) -> int:
+    """Device bytes a request holds while resident: its context workspace
+    plus the image."""
+    p = S.make_params(w.image.shape, str(w.image.dtype), w.E, w.lam, model=w.model,
+                      ps_radius=w.ps_radius, eps=w.eps, max_labels=w.max_labels,
+                      max_particles=capacity)
+    return S.workspace_size(p) + w.image.nbytes
+
+
+def default_capacity(w) -> int:
+    return max(4096, w.labels.size // 4)
+
+
+class Server:
+    """Continuous batching over per-geometry pools.
+
+    hbm_budget: device bytes the resident requests may hold together;
+    slots: slots per pool; tol: flip tolerance (stop when flips < tol * N);
+    max_iters: per-request iteration cap; tick: iterations enqueued per pool
+    between host looks."""
+
+    def __init__(self, hbm_budget: int = 8 << 30, slots: int = 64, tol: float = 1e-3,
+                 max_iters: int = 500, tick: int = 4, mode: int = S.MODE_AUTO):
+        self.budget, self.slots, self.tol = hbm_budget, slots, tol
+        self.max_iters, self.tick, self.mode = max_iters, tick, mode
+        self.pools: dict[tuple, _Pool] = {}
+        self.waiting: collections.deque[Request] = collections.deque()
+        self.finished: list[Request] = []
+        self.used = 0
+        self.t0 = time.perf_counter()
+        self.admit_stream = torch.cuda.Stream()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request):
+        req.footprint = footprint(req.work, default_capacity(req.work))
+        if req.footprint > self.budget:
+            raise ValueError(f"request {req.rid} needs {req.footprint} bytes > budget {self.budget}")
+        self.waiting.append(req)
+
+    # ------------------------------------------------------------ admission
+    def _pool_of(self, w) -> _Pool:
+        key = (w.ndim, float(w.E), float(w.eps))
+        if key not in self.pools:
+            self.pools[key] = _Pool(self.slots)
+        return self.pools[key]
+
+    def _prepare(self):
+        """FIFO: initialise the head request's context while its pool has a
+        slot not yet promised and the budget has room (a head that does not
+        fit waits; nothing overtakes it).  Runs on the admission stream, so
+        it overlaps the pools' work in flight."""
+        while self.waiting:
+            req = self.waiting[0]
+            pool = self._pool_of(req.work)
+            if pool.free_slots() - len(pool.ready) <= 0 or self.used + req.footprint > self.budget:
+                return
+            self.waiting.popleft()
+            w = req.work
+            cap = default_capacity(w)
+            with torch.cuda.stream(self.admit_stream):
+                ctx, img, lab = S.from_workload(w, max_particles=cap)
+                S.init_labels(ctx, img, lab, stream=self.admit_stream)
+                del lab
+            pool.ready.append(_Job(req, ctx, img, cap))
+            self.used += req.footprint
+
+    def _place(self):
+        """Move initialised contexts into free slots; called only while no
+        pool has work in flight (slot tables are read by running kernels)."""
+        for pool in self.pools.values():
+            while pool.ready:
+                k = next(i for i, j in enumerate(pool.jobs) if j is None)
+                job = pool.ready.pop(0)
+                pool.batch.set(k, job.ctx, stream=pool.stream)
+                pool.jobs[k] = job
+                pool.iters[k] = 0
+                job.req.admitted = self.now()
+
+    # ---------------------------------------------------------------- ticks
+    def _retire(self, pool: _Pool, k: int):
+        job = pool.jobs[k]
+        req = job.req
+        pool.batch.set(k, None, stream=pool.stream)
+        req.labels = S.get_labels(job.ctx, stream=pool.stream).cpu().numpy()
+        req.switch_iter = S.gradient_switch(job.ctx, stream=pool.stream)
+        req.iterations = int(pool.iters[k])
+        req.done = self.now()
+        pool.jobs[k] = None
+        self.used -= req.footprint
+        job.ctx.close()
+        self.finished.append(req)
+
+    def step(self) -> bool:
+        """One tick: enqueue iterations on every busy pool (one stream each),
+        admit waiting requests meanwhile, then collect and retire stopped
+        jobs.  Returns whether anything is resident afterwards."""
+        busy = []
+        for pool in self.pools.values():
+            live = pool.live()
+            if not live:
+                continue
+            # never past a resident job's cap, so every stop is exact
+            left = min(self.max_iters - int(pool.iters[k]) for k, _ in live)
+            pool.batch.launch(max(1, min(self.tick, left)), self.tol, self.mode, stream=pool.stream)
+            busy.append(pool)
+        self._prepare()
+        for pool in busy:
+            it, stopped = pool.batch.collect(stream=pool.stream)
+            for k, job in pool.live():
+                pool.iters[k] = it[k]
+                if stopped[k] or it[k] >= self.max_iters:
+                    self._retire(pool, k)
+        # every pool is idle: place what was prepared, then fill freed slots
+        self._place()
+        self._prepare()
+        self._place()
+        return any(p.live() for p in self.pools.values())
+
+    def serve(self, stream_of_requests, realtime: bool = True):
+        """Run a list of (arrival seconds, Workload) to completion.  With
+        realtime, each request is submitted when the clock reaches its arrival
+        time; otherwise all arrive at time 0 (saturation)."""
+        pending = collections.deque(
+            Request(k, w, float(t) if realtime else 0.0) for k, (t, w) in enumerate(stream_of_requests))
+        self.t0 = time.perf_counter()
+        while pending or self.waiting or any(p.live() for p in self.pools.values()):
+            while pending and pending[0].arrival <= self.now():
+                self.submit(pending.popleft())
+            if not self.step() and not self.waiting and pending:
+                time.sleep(max(0.0, min(pending[0].arrival - self.now(), 0.05)))
+        return self.finished
+
+    def close(self):
+        for pool in self.pools.values():
+            for k, job in pool.live():
+                pool.batch.set(k, None, stream=pool.stream)
+                job.ctx.close()
+            for job in pool.ready:
+                job.ctx.close()
+            pool.batch.close()
+        self.pools.clear()
+
+
+def latency_stats(reqs) -> dict:
+    lat = np.array([r.latency for r in reqs])
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    return {"requests": len(reqs), "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+            "images_per_s": len(reqs) / span if span > 0 else float("inf"),
+            "span_s": span}

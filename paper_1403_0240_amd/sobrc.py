@@ -26,7 +26,7 @@ EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "comput
            "get_region_stats", "get_history", "get_gradient_mode", "sobolev_particles_workspace_size",
            "sobolev_smooth_particles", "profile_enable", "profile_read", "batch_workspace_size",
            "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_run",
-           "batch_set_shape", "batch_autotune", "last_error")
+           "batch_launch_iters", "batch_collect", "batch_set_shape", "batch_autotune", "last_error")
 
 
 class SobrcError(RuntimeError):
@@ -81,6 +81,8 @@ def lib():
         "batch_set": [V, I32, V, V],
         "batch_step": [V, I32, V],
         "batch_run": [V, I32, C.c_double, I32, V, V],
+        "batch_launch_iters": [V, I32, C.c_double, I32, V],
+        "batch_collect": [V, V, V, V],
         "batch_set_shape": [V, I32, I32, I32, V],
         "batch_autotune": [V, I32, I32, V, V, V],
     }
@@ -361,6 +363,19 @@ class Batch:
         _check(lib().batch_run(self.handle, max_iters, float(flip_tol), mode,
                                done.ctypes.data_as(C.c_void_p), _stream(stream)))
         return done
+
+    def launch(self, iters: int, flip_tol: float = 0.0, mode=MODE_SOBOLEV, stream=None):
+        """Enqueue iterations without synchronising (see collect)."""
+        _check(lib().batch_launch_iters(self.handle, iters, float(flip_tol), mode, _stream(stream)))
+
+    def collect(self, stream=None):
+        """Synchronise; per slot: iterations since init_labels, stopped flag."""
+        import numpy as np
+        it = np.zeros(self.n_slots, np.int32)
+        st = np.zeros(self.n_slots, np.int32)
+        _check(lib().batch_collect(self.handle, it.ctypes.data_as(C.c_void_p),
+                                   st.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return it, st.astype(bool)
 
     def set_shape(self, part_chunk=0, lg_range=0, sob_tiles=0, stream=None):
         _check(lib().batch_set_shape(self.handle, part_chunk, lg_range, sob_tiles, _stream(stream)))

@@ -15,6 +15,8 @@ The paper's own images (Figs. 3-10) are not available; these stand in for them:
                  with Gaussian noise, shaped like the 3D confocal stack (Fig. 8).
 * ``batch2d``  : 64 independent fp32 images of 128-1024 px sides with 5-30
                  noisy disks/ellipses each (the batched workload).
+* ``serve_stream``: Poisson arrivals of 2D (256^2-2048^2 fp32) and 3D
+                 (64^3-192^3 uint16) piecewise-constant requests (serving).
 * small random multi-label cases and straight/curved contours for the tests.
 
 Pixel (x, y[, z]) has its centre at integer coordinates; arrays are indexed
@@ -177,7 +179,7 @@ def ellipsoids3d(seed: int = 2, n: int = 256, count: int = 25, fg: float = 800.0
         sl[inside2] = 1
     noise = rng.normal(0.0, sigma, size=J.shape).astype(np.float32)
     img = np.clip(np.rint(J + noise), 0, 65535).astype(np.uint16)
-    return Workload("ellipsoids3d_256", img, lab, E=E, lam=lam, model=PC,
+    return Workload(f"ellipsoids3d_{n}", img, lab, E=E, lam=lam, model=PC,
                     iterations=iterations)
 
 
@@ -226,17 +228,20 @@ def digital_disk(n: int, radius: float, E: float, center=None) -> Workload:
     return Workload(f"disk_{n}_{radius}", lab.astype(np.float32), lab, E=E, lam=0.0)
 
 def blobs2d(seed: int = 100, side_lo: int = 128, side_hi: int = 1024, E: float = 8.0,
-            lam: float = 0.18, iterations: int = 200) -> Workload:
+            lam: float = 0.18, iterations: int = 200, square: bool = False) -> Workload:
     """One image of the batched workload: fp32, nx and ny uniform in
-    [128, 1024], 5-30 disks or ellipses (semi-axes from 6 px up to 6 + 8% of
-    the short side, painter's order) of intensity 1.0 on background 0.0,
-    Gaussian noise sigma uniform in [0.2, 0.5].  Initial labels: the shapes
-    shrunk by 2 px.  Piecewise-constant model, E = 8."""
+    [side_lo, side_hi] (one side for both if square), 5-30 disks or ellipses
+    (semi-axes from 6 px up to 6 + 8% of the short side, painter's order) of
+    intensity 1.0 on background 0.0, Gaussian noise sigma uniform in
+    [0.2, 0.5].  Initial labels: the shapes shrunk by 2 px.
+    Piecewise-constant model, E = 8."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    nx, ny = (int(v) for v in rng.integers(side_lo, side_hi + 1, size=2))
+    if square:
+        nx = ny = int(rng.integers(side_lo, side_hi + 1))
+    else:
+        nx, ny = (int(v) for v in rng.integers(side_lo, side_hi + 1, size=2))
     count = int(rng.integers(5, 31))
     sigma = float(rng.uniform(0.2, 0.5))
-    x, y = _grid2d(ny, nx)
     truth = np.zeros((ny, nx), bool)
     lab = np.zeros((ny, nx), dtype=np.int32)
     amax = 6.0 + 0.08 * min(nx, ny)
@@ -245,9 +250,14 @@ def blobs2d(seed: int = 100, side_lo: int = 128, side_hi: int = 1024, E: float =
         b = a if rng.random() < 0.5 else rng.uniform(6.0, amax)  # disk or ellipse
         phi = rng.uniform(0.0, np.pi)
         cx, cy = rng.uniform(amax, nx - amax), rng.uniform(amax, ny - amax)
-        truth |= _inside_ellipse(x, y, cx, cy, a, b, phi)
-        lab[_inside_ellipse(x, y, cx, cy, a, b, phi, shrink=2.0)] = 1
-    img = truth.astype(np.float64) + rng.normal(0.0, sigma, size=(ny, nx))
+        r = int(np.ceil(max(a, b))) + 1
+        x0, x1 = max(int(cx) - r, 0), min(int(cx) + r + 2, nx)
+        y0, y1 = max(int(cy) - r, 0), min(int(cy) + r + 2, ny)
+        xs, ys = _grid2d(y1 - y0, x1 - x0)
+        xs, ys = xs + x0, ys + y0
+        truth[y0:y1, x0:x1] |= _inside_ellipse(xs, ys, cx, cy, a, b, phi)
+        lab[y0:y1, x0:x1][_inside_ellipse(xs, ys, cx, cy, a, b, phi, shrink=2.0)] = 1
+    img = truth.astype(np.float32) + rng.normal(0.0, sigma, size=(ny, nx)).astype(np.float32)
     return Workload(f"blobs2d_{seed}", img.astype(np.float32), lab, E=E, lam=lam, model=PC,
                     iterations=iterations)
 
@@ -256,6 +266,30 @@ def batch2d(n_images: int = 64, seed0: int = 100) -> list:
     """The batched workload: n_images independent blobs2d images, seeds
     seed0 .. seed0 + n_images - 1."""
     return [blobs2d(seed0 + k) for k in range(n_images)]
+
+
+def serve_stream(n_requests: int = 120, rate: float = 50.0, seed: int = 7):
+    """The serving workload: a Poisson arrival stream (exponential gaps of mean
+    1/rate seconds) of independent segmentation requests, 80% 2D fp32 square
+    images of side 256-2048 (blobs2d) and 20% 3D uint16 cubes of side 64-192
+    (ellipsoids3d: 3-12 ellipsoids, semi-axes 6 up to 6 + 12% of the side,
+    800 on 200, Gaussian noise 120).  Returns [(arrival seconds, Workload)]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for k in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        sub = int(rng.integers(0, 2 ** 31))
+        if rng.random() < 0.8:
+            w = blobs2d(sub, side_lo=256, side_hi=2048, square=True)
+        else:
+            n = int(rng.integers(64, 193))
+            amax = 6.0 + 0.12 * n
+            w = ellipsoids3d(sub, n=n, count=int(rng.integers(3, 13)), axes=(6.0, amax),
+                             margin=amax + 2.0)
+        w.name = f"req{k}_{w.name}"
+        out.append((t, w))
+    return out
 
 
 CONFIGS = {

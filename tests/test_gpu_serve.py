@@ -1,0 +1,72 @@
+"""Continuous-batching server: each request's result is the same alone and in
+the mix.
+
+Requests of two kernel geometries (2D and 3D) arrive while others run, wait
+for slots and HBM room, share batches with whatever else is resident, and
+retire on their own.  Each must end with exactly the label field and
+iteration count of its own stand-alone run (AUTO gradients, tolerance stop),
+which test_gpu_parity.py in turn holds to the oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1403_0240_amd import sobrc as S  # noqa: E402
+from paper_1403_0240_amd import serve as SV  # noqa: E402
+from paper_1403_0240_amd import workloads as W  # noqa: E402
+
+TOL, MAX_IT = 1e-3, 120
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S.lib()
+
+
+def requests():
+    out = []
+    for k in range(7):
+        if k % 3 == 2:
+            n = 24 + 4 * k
+            amax = 6.0 + 0.12 * n
+            w = W.ellipsoids3d(500 + k, n=n, count=3, axes=(4.0, amax), margin=amax + 2.0)
+        else:
+            w = W.blobs2d(400 + k, side_lo=48, side_hi=160, square=True)
+        out.append((0.01 * k, w))
+    return out
+
+
+def standalone(w):
+    ctx, img, lab = S.from_workload(w, max_particles=SV.default_capacity(w))
+    S.init_labels(ctx, img, lab)
+    t = S.run(ctx, MAX_IT, TOL, S.MODE_AUTO)
+    return S.get_labels(ctx).cpu().numpy(), t, S.gradient_switch(ctx)
+
+
+@pytest.mark.parametrize("realtime", [False, True])
+def test_each_result_same_alone_and_in_mix(realtime):
+    reqs = requests()
+    print(f"[serve realtime={realtime} n={len(reqs)}]", flush=True)
+    alone = [standalone(w) for _, w in reqs]
+    # two slots per pool and a budget of about three requests: most requests
+    # wait, and are admitted as slots and memory free up
+    fp = sorted(SV.footprint(w, SV.default_capacity(w)) for _, w in reqs)
+    srv = SV.Server(hbm_budget=sum(fp[-3:]), slots=2, tol=TOL, max_iters=MAX_IT, tick=3)
+    done = srv.serve(reqs, realtime=realtime)
+    srv.close()
+    assert len(done) == len(reqs)
+    assert len({r.work.ndim for r in done}) == 2
+    waited = [r for r in done if r.admitted > r.arrival + 1e-4]
+    assert waited, "no request had to wait for a slot"
+    for r in done:
+        L, t, sw = alone[r.rid]
+        assert r.iterations == t, f"request {r.rid}: {r.iterations} iterations, alone {t}"
+        assert r.switch_iter == sw
+        assert np.array_equal(r.labels, L), f"request {r.rid}: labels differ from its stand-alone run"
+        assert r.latency > 0
+    stats = SV.latency_stats(done)
+    assert stats["p99_s"] >= stats["p50_s"] > 0

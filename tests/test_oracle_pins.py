@@ -423,35 +423,48 @@ def test_reversals_count_consecutive_changes(ora, seed):
     assert np.array_equal(stamp.astype(np.int64), last)
 
 
-def test_auto_mode_is_sobolev_then_l2(ora):
+@pytest.mark.parametrize("case", ["disk", "blobs"])
+def test_auto_mode_is_sobolev_then_l2(ora, case):
     """AUTO mode, checked step by step with the plain step function: until the
     switch the iterations are Sobolev iterations, the switch comes at the first
     pair of consecutive oscillating iterations (counted here from label
-    snapshots), and from then on the iterations are L2 iterations.  On this
-    workload the pure Sobolev flow ends in a period-2 oscillation (Eq. (6)
-    remark) and never meets the tolerance; AUTO does."""
-    w = W.disk2d()
+    snapshots), from then on the iterations are L2 iterations, and the run
+    ends at the tolerance or at the second L2 iteration in a row in which every
+    flip is a reversal.  On the disk the pure Sobolev flow ends in a period-2
+    oscillation (Eq. (6) remark) and never meets the tolerance; AUTO does.  On
+    the noisy blobs the L2 flow ends in a settled cycle of a few pixels."""
+    w = W.disk2d() if case == "disk" else W.blobs2d(12, side_lo=256, side_hi=400, square=True)
     P = ora.params_of(w)
     I = w.image.astype(np.float64)
     tol, cap = 1e-3, 200
-    sob = ora.run_ex(P, I, w.labels, ora.MODE_SOBOLEV, cap, tol)
-    assert sob["t"] == cap and sob["switch"] == -1
+    if case == "disk":
+        sob = ora.run_ex(P, I, w.labels, ora.MODE_SOBOLEV, cap, tol)
+        assert sob["t"] == cap and sob["switch"] == -1
     auto = ora.run_ex(P, I, w.labels, ora.MODE_AUTO, cap, tol)
     s = auto["switch"]
     assert 0 < s < auto["t"] < cap
     L = w.labels.copy()
     prev_changed = np.zeros(L.size, bool)
-    osc_prev, expect_switch = False, None
-    for t in range(auto["t"]):
-        mode = ora.MODE_SOBOLEV if expect_switch is None else ora.MODE_L2
+    osc_prev = cyc_prev = False
+    expect_switch, expect_stop, why = None, None, None
+    t = 0
+    while expect_stop is None:
+        mode = ora.MODE_SOBOLEV if expect_switch is None or t < expect_switch else ora.MODE_L2
         L_next, info = ora.step(P, I, L, mode, want_arrays=False)
         changed = (L_next != L).reshape(-1)
         f, r = int(changed.sum()), int((changed & prev_changed).sum())
         assert (info["n"], f, r) == (auto["n"][t], auto["flips"][t], auto["reversals"][t])
-        osc = f > 0 and 2 * r >= f
+        osc, cyc = f > 0 and 2 * r >= f, f > 0 and r == f
+        l2_both = expect_switch is not None and t - 1 >= expect_switch
+        if f < tol * info["n"]:
+            expect_stop, why = t + 1, "tolerance"
+        elif l2_both and cyc and cyc_prev:
+            expect_stop, why = t + 1, "cycle"
         if expect_switch is None and osc and osc_prev:
             expect_switch = t + 1
-        osc_prev, prev_changed, L = osc, changed, L_next
-    assert expect_switch == s
+        osc_prev, cyc_prev, prev_changed, L = osc, cyc, changed, L_next
+        t += 1
+        assert t <= cap
+    assert expect_switch == s and expect_stop == auto["t"]
+    assert why == ("tolerance" if case == "disk" else "cycle")
     assert np.array_equal(L, auto["L"])
-    assert auto["flips"][-1] < tol * auto["n"][-1]
