@@ -135,6 +135,8 @@ Geom make_geom(const sobrc_params* p)
         ++g.lgRe;
     g.Re = 1 << g.lgRe;
     g.ge = (g.ntiles + g.Re - 1) >> g.lgRe;
+    // a flat dirty list pays when an emission block holds many tiles
+    g.dlistm = g.ge <= kMaxGrid && g.Re >= 8 ? 1 : 0;
     // Sobolev kernel: dense LDS brick for (ndim, h) when instantiated, else
     // the generic staged scan
     g.brick = g.h >= 1 && g.h <= (g.ndim == 3 ? kBrickMaxH3 : kBrickMaxH2);
@@ -167,7 +169,7 @@ void kernel_table(double E, double eps, int T, float* W)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t lab, fstamp, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
+    size_t lab, fstamp, dcnt, dlist, dflat, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
         part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, ds;
     size_t total;
 };
@@ -184,6 +186,9 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     };
     L.lab = take((size_t)nvox * 2);
     L.fstamp = take((size_t)nvox * 4);
+    L.dcnt = take((size_t)g.ge * 4);
+    L.dlist = take((size_t)g.ge * kBlock * 4);
+    L.dflat = take((size_t)g.ntiles * 4);
     L.rec0 = take((size_t)cap * 8);
     L.rec1 = take((size_t)cap * 8);
     L.ts0 = take((size_t)(g.ntiles + 1) * 4);
@@ -217,6 +222,9 @@ Bufs carve(const Layout& L, char* base, long long cap)
     Bufs b{};
     b.lab = (unsigned short*)(base + L.lab);
     b.fstamp = (unsigned*)(base + L.fstamp);
+    b.dcnt = (unsigned*)(base + L.dcnt);
+    b.dlist = (unsigned*)(base + L.dlist);
+    b.dflat = (unsigned*)(base + L.dflat);
     b.rec[0] = (uint2*)(base + L.rec0);
     b.rec[1] = (uint2*)(base + L.rec1);
     b.tstart[0] = (unsigned*)(base + L.ts0);
@@ -776,6 +784,7 @@ Geom slot_geom(const sobrc_batch* B, const sobrc_ctx* c)
         g.lgRe = lg;
         g.Re = 1 << lg;
         g.ge = (g.ntiles + g.Re - 1) >> lg;
+        g.dlistm = g.ge <= kMaxGrid && g.Re >= 8 ? 1 : 0;  // the list buffers are always there
     }
     if (B->sob_tiles > 0) {
         int sg = (g.ntiles + B->sob_tiles - 1) / B->sob_tiles;

@@ -76,6 +76,7 @@ struct Geom {
     int stage_cap;              // generic-path staging capacity
     int sob_lds;                // dynamic LDS bytes of the generic Sobolev kernel
     int sob_grid;               // blocks of the Sobolev kernels (multiple of 8)
+    int dlistm;                 // dirty tiles go through a flat list balanced over all waves (ge <= kMaxGrid)
 };
 
 // Device-resident control block of a context.
@@ -95,6 +96,7 @@ struct DevState {
                             // start); bit 1: the last committed step oscillated (reversals >= flips / 2);
                             // bit 2: every flip of the last committed step was a reversal
     unsigned switch_it;     // 1 + first iteration run with L2 gradients in auto mode, 0: none yet
+    unsigned ndirty;        // dirty tiles of the running step (flat list, when listed)
 };
 
 // A block's place in the work of one context: its index and the block count
@@ -117,6 +119,9 @@ struct Bufs {
     unsigned* tcnt;          // per-tile particle count of the next state
     unsigned* dirty;         // epoch of the last flip within one pixel of the tile
     unsigned* fstamp;        // per pixel: 1 + the last iteration that changed its label (0: never)
+    unsigned* dcnt;          // per emission block: dirty tiles it listed
+    unsigned* dlist;         // per emission block: its dirty tiles (kBlock entries each)
+    unsigned* dflat;         // dirty tiles of the step, flat (ntiles entries)
     unsigned* tslot;         // per tile: emission bitmasks from k_count for k_write
     float* dE;               // L2 gradient, capacity
     float* gH1;              // Sobolev gradient, capacity
@@ -152,6 +157,7 @@ struct ImgDesc {
 // multiple of 8 so that item & 7 names the XCD as in a stand-alone launch.
 enum { kPhPart = 0, kPhEmit = 1, kPhSob = 2, kPhScan = 3, kNumPh = 4 };
 constexpr int kPersist = 2048;  // blocks of a persistent batched launch
+constexpr int kListGrid = 1024;  // blocks of the dirty-list count (all resident at once)
 
 struct BatchTab {
     const ImgDesc* d;     // nslot descriptors

@@ -368,29 +368,88 @@ __device__ void wave_load_box(const Geom& g, const unsigned short* __restrict__ 
     wave_lds_sync();
 }
 
-// Particles of tile t under the current labels, counted by one wave.  A box
-// (tile + one-pixel halo) holding two labels lo < hi takes the bit path: per
-// box row, masks of "label == lo" and "label == hi"; a pixel is a particle iff
-// its 3x3(x3) neighbourhood holds both labels, i.e. iff the OR of the dilated
-// masks over the neighbourhood is set in both.  The tile's slot keeps, per
-// tile row, the particle bits and the bits of pixels labelled lo, so the
-// records can be written later without the labels; other boxes are marked
-// for a full re-enumeration (slot word 0 = 0xFFFF).
+// Particles of tile t under the current labels, counted by one wave.  Each
+// lane holds whole rows of the box (tile + one-pixel halo) in registers: the
+// box's labels, whether it holds two labels lo < hi or more, and the per-row
+// masks of "label == lo" and "label == hi" come out of registers without LDS
+// round trips.  With two labels a pixel is a particle iff its 3x3(x3)
+// neighbourhood holds both, i.e. iff the OR of the dilated masks over the
+// neighbourhood is set in both.  The tile's slot keeps, per tile row, the
+// particle bits, the bits of pixels labelled lo and the particles before the
+// row, so records can be written later without the labels; boxes with more
+// labels are enumerated from an LDS copy and marked for a full re-enumeration
+// (slot word 0 = 0xFFFF).
+template <int ND>
 __device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restrict__ lab, unsigned t,
                                     WaveEmit& W, unsigned* __restrict__ slot)
 {
+    constexpr int TX = ND == 3 ? 8 : 16, TY = TX, TZ = ND == 3 ? 8 : 1, HZ = ND == 3 ? 1 : 0;
+    constexpr int BX = TX + 2, BY = TY + 2, BZ = TZ + 2 * HZ, NROW = BY * BZ;
+    constexpr int RPL = (NROW + 63) / 64;  // box rows per lane
+    static_assert(BX * BY * BZ <= kBoxMax / 2 && NROW <= 128, "box too large");
     const int lane = lane_id();
-    TileInfo ti = tile_info(g, t);
-    wave_load_box(g, lab, W.box, ti);
-    const int nbox = ti.BX * ti.BY * ti.BZ;
-    unsigned mn = 0xffffu, mx = 0u;
-    for (int k = lane; k < nbox; k += 64) {
-        unsigned l = W.box[k];
-        if (l != kNone) {
-            mn = l < mn ? l : mn;
-            mx = l > mx ? l : mx;
+    const int tx = (int)(t % (unsigned)g.ntx), ty = (int)((t / (unsigned)g.ntx) % (unsigned)g.nty);
+    const int tz = (int)(t / ((unsigned)g.ntx * (unsigned)g.nty));
+    const int ox = tx * TX - 1, oy = ty * TY - 1, oz = tz * TZ - HZ;
+    // every lane issues all of its loads before using any.  With rows of a
+    // multiple of 8 labels (16-byte aligned rows) a box row is read as the
+    // aligned 16-byte chunks of [tx*TX - 8, tx*TX + TX + 8); chunks outside
+    // the row are not read.  Otherwise each label is read on its own.
+    constexpr int NCH = (TX + 16) / 8;  // 16-byte chunks per box row
+    unsigned v[RPL][BX];
+    if ((g.nx & 7) == 0) {
+        uint4 ch[RPL][NCH];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = lane + 64 * i;
+            const int by = r % BY, bz = r / BY;
+            const int y = oy + by, z = oz + bz;
+            const bool rin = r < NROW && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+            const uint4* row = (const uint4*)(lab + (rin ? lin_of(g, 0, y, z) : 0));
+            const int c0 = tx * (TX / 8) - 1;  // chunk index of x = tx*TX - 8
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int cc = c0 + c;
+                const bool cin = rin && cc >= 0 && 8 * cc + 8 <= g.nx;
+                ch[i][c] = cin ? row[cc] : make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+#pragma unroll
+            for (int bx = 0; bx < BX; ++bx) {
+                const int e = 7 + bx;  // label index inside the 8 * NCH window
+                const uint4 q = ch[i][e >> 3];
+                const int w = (e >> 1) & 3;
+                const unsigned word = w == 0 ? q.x : w == 1 ? q.y : w == 2 ? q.z : q.w;
+                v[i][bx] = (e & 1) ? (word >> 16) : (word & 0xffffu);
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = lane + 64 * i;
+            const int by = r % BY, bz = r / BY;
+            const int y = oy + by, z = oz + bz;
+            const bool rin = r < NROW && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+            const long long base = rin ? lin_of(g, 0, y, z) : 0;
+#pragma unroll
+            for (int bx = 0; bx < BX; ++bx) {
+                const int x = ox + bx;
+                v[i][bx] = (rin && x >= 0 && x < g.nx) ? (unsigned)lab[base + x] : (unsigned)kNone;
+            }
         }
     }
+    unsigned mn = 0xffffu, mx = 0u;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) {
+            const unsigned l = v[i][bx];
+            if (l != kNone) {
+                mn = l < mn ? l : mn;
+                mx = l > mx ? l : mx;
+            }
+        }
     for (int o = 32; o > 0; o >>= 1) {
         unsigned a = __shfl_xor(mn, o), c = __shfl_xor(mx, o);
         mn = a < mn ? a : mn;
@@ -399,59 +458,75 @@ __device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restr
     if (mx <= mn)
         return 0;  // one label: no contour in this tile
     bool third = false;
-    for (int k = lane; k < nbox; k += 64) {
-        unsigned l = W.box[k];
-        third = third || (l != kNone && l != mn && l != mx);
-    }
-    const int BXY = ti.BX * ti.BY, zr = ti.hz;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) {
+            const unsigned l = v[i][bx];
+            third = third || (l != kNone && l != mn && l != mx);
+        }
+    constexpr int BXY = BX * BY;
     if (__ballot(third) != 0) {
-        const int nv = ti.TX * ti.TY * ti.TZ;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = lane + 64 * i;
+            if (r < NROW)
+#pragma unroll
+                for (int bx = 0; bx < BX; ++bx)
+                    W.box[r * BX + bx] = (unsigned short)v[i][bx];
+        }
+        wave_lds_sync();
         unsigned cc = 0;
-        for (int v = lane; v < nv; v += 64) {
-            int lx = v & (ti.TX - 1), ly = (v >> g.tsx) & (ti.TY - 1), lz = v >> (g.tsx + g.tsy);
-            int x = ti.tx * ti.TX + lx, y = ti.ty * ti.TY + ly, z = ti.tz * ti.TZ + lz;
+        for (int q = lane; q < TX * TY * TZ; q += 64) {
+            const int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
+            const int x = tx * TX + lx, y = ty * TY + ly, z = tz * TZ + lz;
             if (x >= g.nx || y >= g.ny || z >= g.nz)
                 continue;
-            int cidx = (lx + 1) + ti.BX * ((ly + 1) + ti.BY * (lz + ti.hz));
+            const int cidx = (lx + 1) + BX * ((ly + 1) + BY * (lz + HZ));
             int lo, hi;
-            cc += neighbour_span(W.box, cidx, ti.BX, BXY, zr, W.box[cidx], lo, hi);
+            cc += neighbour_span(W.box, cidx, BX, BXY, HZ, W.box[cidx], lo, hi);
         }
         if (lane == 0)
             slot[0] = 0xffffu;
         return wave_sum_u(cc);
     }
-    const int nrow = ti.BY * ti.BZ;
-    for (int r = lane; r < nrow; r += 64) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int r = lane + 64 * i;
         unsigned ml = 0, mh = 0;
-        for (int bx = 0; bx < ti.BX; ++bx) {
-            unsigned l = W.box[r * ti.BX + bx];
-            ml |= (l == mn ? 1u : 0u) << bx;
-            mh |= (l == mx ? 1u : 0u) << bx;
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) {
+            ml |= (v[i][bx] == mn ? 1u : 0u) << bx;
+            mh |= (v[i][bx] == mx ? 1u : 0u) << bx;
         }
-        W.mlo[r] = ml;
-        W.mhi[r] = mh;
+        if (r < NROW) {
+            W.mlo[r] = ml;
+            W.mhi[r] = mh;
+        }
     }
     wave_lds_sync();
     unsigned pb = 0;
-    if (lane < ti.TY * ti.TZ) {  // one interior row per lane (at most 64)
-        int by = (lane & (ti.TY - 1)) + 1, bz = (lane >> g.tsy) + ti.hz;
+    if (lane < TY * TZ) {  // one interior row per lane (at most 64)
+        const int by = lane % TY + 1, bz = lane / TY + HZ;
         unsigned ol = 0, oh = 0;
-        for (int dz = -zr; dz <= zr; ++dz)
+#pragma unroll
+        for (int dz = -HZ; dz <= HZ; ++dz)
+#pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
-                int r = (by + dy) + ti.BY * (bz + dz);
-                unsigned ml = W.mlo[r], mh = W.mhi[r];
+                const int r = (by + dy) + BY * (bz + dz);
+                const unsigned ml = W.mlo[r], mh = W.mhi[r];
                 ol |= ml | (ml << 1) | (ml >> 1);
                 oh |= mh | (mh << 1) | (mh >> 1);
             }
-        int rc = by + ti.BY * bz;
-        unsigned cl = W.mlo[rc], ch = W.mhi[rc];
-        unsigned tmask = (1u << ti.TX) - 1u;
+        const int rc = by + BY * bz;
+        const unsigned cl = W.mlo[rc], ch = W.mhi[rc];
+        constexpr unsigned tmask = (1u << TX) - 1u;
         pb = ((ol & oh & (cl | ch)) >> 1) & tmask;
         slot[1 + lane] = pb | (((cl >> 1) & tmask) << 16);
     }
     unsigned tot;
     const unsigned pre = wave_excl_scan_u((unsigned)__popc(pb), tot);
-    if (lane < ti.TY * ti.TZ)
+    if (lane < TY * TZ)
         slot[1 + kSlotRows + lane] = pre;
     if (lane == 0)
         slot[0] = mn | (mx << 16);
@@ -540,6 +615,7 @@ __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned e
 
 // Particle count of every tile of the next state, accumulated per range.
 // Clean tiles keep their previous count.
+template <int ND>
 __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, VB vb)
 {
     __shared__ WaveEmit W[kBlock / 64];
@@ -568,10 +644,17 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     }
     __syncthreads();
     const unsigned ndl = s_ndl;
+    if (g.dlistm) {  // list them; count_list_body balances them over all waves
+        for (unsigned k = threadIdx.x; k < ndl; k += kBlock)
+            b.dlist[(size_t)vb.id * kBlock + k] = s_dl[k];
+        if (threadIdx.x == 0)
+            b.dcnt[vb.id] = ndl;
+        return;
+    }
     const int wv = threadIdx.x >> 6;
     for (unsigned i = wv; i < ndl; i += kBlock / 64) {
         const unsigned td = s_dl[i];
-        unsigned cc = wave_count_tile(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
+        unsigned cc = wave_count_tile<ND>(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
             b.tcnt[td] = cc;
             if (cc) {
@@ -582,9 +665,74 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     }
 }
 
+template <int ND>
 __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int gated, int all_dirty)
 {
-    count_body(g, b, cur, gated, all_dirty, VB{blockIdx.x, gridDim.x});
+    count_body<ND>(g, b, cur, gated, all_dirty, VB{blockIdx.x, gridDim.x});
+}
+
+// Dirty tiles listed by count_body, counted with one wave each: every block
+// forms the exclusive prefix of the per-block list lengths and the waves of
+// all blocks take list items round-robin, so a cluster of dirty tiles in one
+// emission block no longer serialises on its four waves.  The items also go
+// to a flat list for the write kernel.
+template <int ND>
+__device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, int gated, VB vb)
+{
+    __shared__ WaveEmit W[kBlock / 64];
+    __shared__ unsigned s_pre[kMaxGrid + 1];
+    __shared__ unsigned s_red[kBlock / 64];
+    if (gated && stopped(b.ds))
+        return;
+    constexpr int kPer = kMaxGrid / kBlock;  // list lengths per thread
+    const int ge = g.ge;
+    const int i0 = (int)threadIdx.x * kPer;
+    unsigned c[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        c[k] = i0 + k < ge ? b.dcnt[i0 + k] : 0u;
+        sum += c[k];
+    }
+    unsigned tot;
+    unsigned ex = block_exscan_u(sum, s_red, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (i0 + k < ge)
+            s_pre[i0 + k] = ex;
+        ex += c[k];
+    }
+    if (threadIdx.x == 0)
+        s_pre[ge] = tot;
+    __syncthreads();
+    if (vb.id == 0 && threadIdx.x == 0)
+        b.ds->ndirty = tot;
+    const int wv = threadIdx.x >> 6;
+    for (unsigned item = vb.id * (kBlock / 64) + wv; item < tot; item += vb.n * (kBlock / 64)) {
+        int lo = 0, hi = ge;  // list block holding item: the largest lo with s_pre[lo] <= item
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const unsigned td = b.dlist[(size_t)lo * kBlock + (item - s_pre[lo])];
+        unsigned cc = wave_count_tile<ND>(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
+        if (lane_id() == 0) {
+            b.dflat[item] = td;
+            b.tcnt[td] = cc;
+            if (cc) {
+                atomicAdd(&b.part_cnt[td >> g.lgRe], cc);
+                atomicAdd(&b.part_act[td >> g.lgRe], 1u);
+            }
+        }
+    }
+}
+
+template <int ND>
+__global__ __launch_bounds__(kBlock) void k_count_list(Geom g, Bufs b, int gated)
+{
+    count_list_body<ND>(g, b, gated, VB{blockIdx.x, gridDim.x});
 }
 
 template <typename T>
@@ -890,6 +1038,23 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
             if (dst[u] != 0xffffffffu)
                 rec[dst[u]] = r[u];
     }
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    if (g.dlistm) {
+        // dirty tiles from the flat list, round-robin over all waves
+        const unsigned nd = ds->ndirty;
+        for (unsigned item = vb.id * (kBlock / 64) + wv; item < nd; item += vb.n * (kBlock / 64)) {
+            const unsigned tt = b.dflat[item];
+            if (!b.tcnt[tt])
+                continue;
+            const int r0 = (int)(tt >> g.lgRe) << g.lgRe;
+            unsigned part = 0;  // offset: the range's base plus the counts before tt in the range
+            for (int k = r0 + lane; k < (int)tt; k += 64)
+                part += b.tcnt[k];
+            unsigned o = b.part_off[tt >> g.lgRe] + wave_sum_u(part);
+            wave_write_tile(g, b.lab, tt, W[wv], b.tslot + (size_t)tt * kSlotWords, rec, o);
+        }
+        return;
+    }
     // dirty tiles of this block's round-robin share are re-emitted from the labels
     const unsigned G = vb.n;
     const unsigned jd = vb.id + threadIdx.x * G;
@@ -898,7 +1063,6 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
         s_dl[atomicAdd(&s_ndl, 1u)] = td;
     __syncthreads();
     const unsigned ndl = s_ndl;
-    const int wv = threadIdx.x >> 6, lane = lane_id();
     for (unsigned i = wv; i < ndl; i += kBlock / 64) {
         const unsigned tt = s_dl[i];
         const int r0 = (int)(tt >> g.lgRe) << g.lgRe;
@@ -1712,7 +1876,17 @@ hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, c
 
 hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_count, dim3(g.ge), dim3(kBlock), 0, s, g, b, cur, gated, all_dirty);
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_count<3>, dim3(g.ge), dim3(kBlock), 0, s, g, b, cur, gated, all_dirty);
+    else
+        hipLaunchKernelGGL(k_count<2>, dim3(g.ge), dim3(kBlock), 0, s, g, b, cur, gated, all_dirty);
+    if (g.dlistm) {
+        const unsigned gl = g.ge < kListGrid ? (unsigned)g.ge : (unsigned)kListGrid;
+        if (g.ndim == 3)
+            hipLaunchKernelGGL(k_count_list<3>, dim3(gl), dim3(kBlock), 0, s, g, b, gated);
+        else
+            hipLaunchKernelGGL(k_count_list<2>, dim3(gl), dim3(kBlock), 0, s, g, b, gated);
+    }
     return hipGetLastError();
 }
 
@@ -1864,6 +2038,7 @@ __global__ __launch_bounds__(kBlock) void kb_flip(const ImgDesc* __restrict__ d,
     }
 }
 
+template <int ND>
 __global__ __launch_bounds__(kBlock) void kb_count(const ImgDesc* __restrict__ d, const unsigned* __restrict__ par,
                                                   const unsigned* __restrict__ offs, int nslot)
 {
@@ -1874,7 +2049,23 @@ __global__ __launch_bounds__(kBlock) void kb_count(const ImgDesc* __restrict__ d
         const ImgDesc& D = d[i];
         const unsigned v = item - off[i];
         if (v < (unsigned)D.g.ge)
-            count_body(D.g, D.b, (int)par[i], 1, 0, VB{v, (unsigned)D.g.ge});
+            count_body<ND>(D.g, D.b, (int)par[i], 1, 0, VB{v, (unsigned)D.g.ge});
+        __syncthreads();
+    }
+}
+
+template <int ND>
+__global__ __launch_bounds__(kBlock) void kb_count_list(const ImgDesc* __restrict__ d,
+                                                       const unsigned* __restrict__ offs, int nslot)
+{
+    const unsigned* off = offs + kPhEmit * (nslot + 1);
+    const unsigned total = off[nslot];
+    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
+        const int i = slot_of(off, nslot, item);
+        const ImgDesc& D = d[i];
+        const unsigned v = item - off[i];
+        if (v < (unsigned)D.g.ge && D.g.dlistm)
+            count_list_body<ND>(D.g, D.b, 1, VB{v, (unsigned)D.g.ge});
         __syncthreads();
     }
 }
@@ -1983,7 +2174,15 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
     }
     hipLaunchKernelGGL(kb_flip, persistent_grid(totals[kPhPart]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
                        flags);
-    hipLaunchKernelGGL(kb_count, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns);
+    if (g0.ndim == 3) {
+        hipLaunchKernelGGL(kb_count<3>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off,
+                           ns);
+        hipLaunchKernelGGL(kb_count_list<3>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.off, ns);
+    } else {
+        hipLaunchKernelGGL(kb_count<2>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off,
+                           ns);
+        hipLaunchKernelGGL(kb_count_list<2>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.off, ns);
+    }
     const unsigned nsc = totals[kPhScan] < 256u ? (totals[kPhScan] ? totals[kPhScan] : 1u) : 256u;
     hipLaunchKernelGGL(kb_scan, dim3(nsc), dim3(kScanThreads), 0, s, t.d, t.par, t.off, ns, tol, flags);
     hipLaunchKernelGGL(kb_write, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
