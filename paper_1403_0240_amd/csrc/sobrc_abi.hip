@@ -186,7 +186,7 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     };
     L.lab = take((size_t)nvox * 2);
     L.fstamp = take((size_t)nvox * 4);
-    L.dcnt = take((size_t)g.ge * 4);
+    L.dcnt = take((size_t)kMaxGrid * 4);  // read as whole 16-byte groups
     L.dlist = take((size_t)g.ge * kBlock * 4);
     L.dflat = take((size_t)g.ntiles * 4);
     L.rec0 = take((size_t)cap * 8);
@@ -262,8 +262,18 @@ int32_t upload_tables(const Geom& g, double E, double eps, float* d_W, SobW* sw,
     kernel_table(E, eps, g.T, W);
     for (int k = 0; k < kMaxLim; ++k) {
         sw->w[k] = k < g.T ? W[k] : 0.f;
-        sw->m[k] = k < g.T ? 1u : 0u;
+        sw->rw[k] = -1;
     }
+    const int hz = g.ndim == 3 ? g.h : 0;
+    for (int dz = -hz; dz <= hz; ++dz)
+        for (int dy = -g.h; dy <= g.h; ++dy) {
+            int w = -1;
+            while (w + 1 <= g.h && (w + 1) * (w + 1) + dy * dy + dz * dz < g.T)
+                ++w;
+            const int k = (dy + g.h) + (2 * g.h + 1) * (dz + hz);
+            if (k < kMaxLim)
+                sw->rw[k] = w;
+        }
     SOBRC_HIP(hipMemcpyAsync(d_W, W, sizeof W, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     // the host array is reused by the next call: wait for the copy
     SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");

@@ -27,24 +27,32 @@ constexpr int kSlotWords = 1 + 2 * kSlotRows;
 constexpr int kBrickMaxH3 = 4;
 constexpr int kBrickMaxH2 = 8;
 
-// LDS bytes of a brick kernel: the dense brick (two fp32 values and one packed
-// count word per cell) or, if larger, the generic path's staging of 256
-// particles with its weight table.
+// LDS bytes of a brick kernel: the dense brick (two fp32 values per cell) and
+// two side bitmasks per box row or, if larger, the generic path's staging of
+// 256 particles with its weight table.
 __host__ __device__ constexpr int brick_cells(int nd, int h)
 {
-    return nd == 3 ? (8 + 2 * h) * (8 + 2 * h) * (8 + 2 * h) : (16 + 2 * h) * (16 + 2 * h);
+    // rows padded to an odd stride (see the brick kernels)
+    return nd == 3 ? ((8 + 2 * h) | 1) * (8 + 2 * h) * (8 + 2 * h) : ((16 + 2 * h) | 1) * (16 + 2 * h);
+}
+__host__ __device__ constexpr int brick_rows(int nd, int h)
+{
+    return nd == 3 ? (8 + 2 * h) * (8 + 2 * h) : (16 + 2 * h);
 }
 __host__ __device__ constexpr int brick_lds_bytes(int nd, int h)
 {
-    return brick_cells(nd, h) * 12 > 256 * 12 + kMaxLim * 4 + 16 ? brick_cells(nd, h) * 12
-                                                                   : 256 * 12 + kMaxLim * 4 + 16;
+    return brick_cells(nd, h) * 8 + brick_rows(nd, h) * 8 > 256 * 12 + kMaxLim * 4 + 16
+               ? brick_cells(nd, h) * 8 + brick_rows(nd, h) * 8
+               : 256 * 12 + kMaxLim * 4 + 16;
 }
 
 // Kernel weights by integer squared distance: w[d2] = K(sqrt(d2)) inside the
-// support (d2 < T), 0 outside; m[d2] = 1 inside, 0 outside.
+// support (d2 < T), 0 outside.  Support rows: rw[(dy + h) + (2h + 1)(dz + hz)]
+// is the largest dx >= 0 with dx^2 + dy^2 + dz^2 < T, or -1 if there is none
+// (h = halo, hz = h in 3D and 0 in 2D).
 struct SobW {
     float w[kMaxLim];
-    unsigned m[kMaxLim];
+    int rw[kMaxLim];
 };
 
 // error bits kept on the device (sticky until init_labels)
@@ -121,7 +129,7 @@ struct Bufs {
     unsigned* fstamp;        // per pixel: 1 + the last iteration that changed its label (0: never)
     unsigned* dcnt;          // per emission block: dirty tiles it listed
     unsigned* dlist;         // per emission block: its dirty tiles (kBlock entries each)
-    unsigned* dflat;         // dirty tiles of the step, flat (ntiles entries)
+    unsigned* dflat;         // dirty tiles of the step, flat: positions in dlist (ntiles entries)
     unsigned* tslot;         // per tile: emission bitmasks from k_count for k_write
     float* dE;               // L2 gradient, capacity
     float* gH1;              // Sobolev gradient, capacity

@@ -672,10 +672,11 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
 }
 
 // Dirty tiles listed by count_body, counted with one wave each: every block
-// forms the exclusive prefix of the per-block list lengths and the waves of
-// all blocks take list items round-robin, so a cluster of dirty tiles in one
-// emission block no longer serialises on its four waves.  The items also go
-// to a flat list for the write kernel.
+// forms the exclusive prefix of the per-block list lengths (two 16-byte loads
+// per thread) and the waves of all blocks take list items round-robin, so a
+// cluster of dirty tiles in one emission block no longer serialises on its
+// four waves.  The items also go to a flat list (positions in the per-block
+// lists) for the write kernel.
 template <int ND>
 __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, int gated, VB vb)
 {
@@ -684,19 +685,22 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     __shared__ unsigned s_red[kBlock / 64];
     if (gated && stopped(b.ds))
         return;
-    constexpr int kPer = kMaxGrid / kBlock;  // list lengths per thread
+    static_assert(kMaxGrid == 8 * kBlock, "eight list lengths per thread");
     const int ge = g.ge;
-    const int i0 = (int)threadIdx.x * kPer;
-    unsigned c[kPer], sum = 0;
+    const int i0 = (int)threadIdx.x * 8;
+    const uint4* dc = (const uint4*)b.dcnt;  // kMaxGrid entries; those >= ge are ignored
+    const uint4 q0 = dc[2 * threadIdx.x], q1 = dc[2 * threadIdx.x + 1];
+    unsigned c[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    unsigned sum = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        c[k] = i0 + k < ge ? b.dcnt[i0 + k] : 0u;
+    for (int k = 0; k < 8; ++k) {
+        c[k] = i0 + k < ge ? c[k] : 0u;
         sum += c[k];
     }
     unsigned tot;
     unsigned ex = block_exscan_u(sum, s_red, &tot);
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
+    for (int k = 0; k < 8; ++k) {
         if (i0 + k < ge)
             s_pre[i0 + k] = ex;
         ex += c[k];
@@ -716,10 +720,11 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
             else
                 hi = mid;
         }
-        const unsigned td = b.dlist[(size_t)lo * kBlock + (item - s_pre[lo])];
+        const unsigned pos = (unsigned)lo * kBlock + (item - s_pre[lo]);
+        const unsigned td = b.dlist[pos];
         unsigned cc = wave_count_tile<ND>(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
-            b.dflat[item] = td;
+            b.dflat[item] = pos;
             b.tcnt[td] = cc;
             if (cc) {
                 atomicAdd(&b.part_cnt[td >> g.lgRe], cc);
@@ -1043,7 +1048,7 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
         // dirty tiles from the flat list, round-robin over all waves
         const unsigned nd = ds->ndirty;
         for (unsigned item = vb.id * (kBlock / 64) + wv; item < nd; item += vb.n * (kBlock / 64)) {
-            const unsigned tt = b.dflat[item];
+            const unsigned tt = b.dlist[b.dflat[item]];
             if (!b.tcnt[tt])
                 continue;
             const int r0 = (int)(tt >> g.lgRe) << g.lgRe;
@@ -1346,12 +1351,19 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_generic(Geom g, Bufs b, i
     sobolev_generic_body(g, b, cur, in, out, gated, VB{blockIdx.x, gridDim.x});
 }
 
+constexpr int kTapGroup = 16;  // brick reads the stencil keeps in flight
+
 template <int ND, int H>
 struct BrickShape {
     static constexpr int TX = ND == 3 ? 8 : 16, TY = TX, TZ = ND == 3 ? 8 : 1;
     static constexpr int HZ = ND == 3 ? H : 0;
     static constexpr int BX = TX + 2 * H, BY = TY + 2 * H, BZ = TZ + 2 * HZ;
-    static constexpr int NCELL = BX * BY * BZ;
+    // odd row stride: the rows of a tile then fall on distinct LDS banks
+    // (a stride that is a multiple of 4 puts all (y, z) rows of a plane on
+    // 8 of the 32 bank pairs, so a surface with one particle per row
+    // conflicts 4-8 ways on every tap)
+    static constexpr int SX = BX | 1;
+    static constexpr int NCELL = SX * BY * BZ;
     static constexpr int LIM = (H + 1) * (H + 1);
     static constexpr int count()
     {
@@ -1382,7 +1394,7 @@ constexpr TapList<BrickShape<ND, H>::NT> make_taps()
             for (int dx = -H; dx <= H; ++dx) {
                 int d2 = dx * dx + dy * dy + dz * dz;
                 if (d2 < S::LIM) {
-                    t.off[k] = (dx + H) + S::BX * ((dy + H) + S::BY * (dz + S::HZ));
+                    t.off[k] = (dx + H) + S::SX * ((dy + H) + S::BY * (dz + S::HZ));
                     t.d2[k] = d2;
                     ++k;
                 }
@@ -1397,11 +1409,21 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
     constexpr TapList<S::NT> taps = make_taps<ND, H>();
     constexpr int NCORE = S::TX * S::TY * S::TZ;
     __shared__ __align__(16) char lds[brick_lds_bytes(ND, H)];
-    __shared__ unsigned s_core[NCORE];          // own particles: brick corner cell | side A << 31
-    __shared__ unsigned s_beg[32], s_tile[32], s_lxy[32], s_lz[32], s_rpre[33];
-    __shared__ unsigned s_mode, s_ncore;
-    float2* s_v = (float2*)lds;                   // (value of a lo->hi particle, value of a hi->lo particle)
-    unsigned* s_n = (unsigned*)(s_v + S::NCELL);  // their counts, packed lo->hi | hi->lo << 16
+    // own particles: brick corner cell (12 bits) | x in tile << 12 | box row of
+    // the corner << 17 | side A << 31
+    __shared__ unsigned s_core[NCORE];
+    __shared__ unsigned s_mode, s_ncore, s_cs;
+    // row tasks per thread: the box spans at most three tiles in x
+    constexpr int RT = (3 * S::BY * S::BZ + kSobBlock - 1) / kSobBlock;
+    constexpr int NROWS = S::BY * S::BZ;
+    static_assert(S::NCELL * 8 + NROWS * 8 <= brick_lds_bytes(ND, H), "brick does not fit its LDS");
+    // fields of a core entry: corner cells and rows of the tile's own pixels;
+    // the support window of a row fits one 32-bit mask
+    static_assert((S::TX - 1) + S::SX * ((S::TY - 1) + S::BY * (S::TZ - 1)) < 4096 &&
+                      (S::TY - 1) + S::BY * (S::TZ - 1) < 512 && S::TX <= 32 && S::BX <= 32,
+                  "core entry fields");
+    float2* s_v = (float2*)lds;               // (value of a lo->hi particle, value of a hi->lo particle)
+    uint2* s_m = (uint2*)(s_v + S::NCELL);    // per box row: bits of lo->hi particles, of hi->lo particles
     DevState* ds = b.ds;
     if ((gated & kGate) && stopped(ds))
         return;
@@ -1424,137 +1446,163 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
         const int kz0 = bz0 / S::TZ, nkz = (bz1 - 1) / S::TZ - kz0 + 1;
         const int nnt = nkx * nky * nkz;
         const int kown = (tx - kx0) + nkx * ((ty - ky0) + nky * (tz - kz0));
+        const int BYe = by1 - by0, BZe = bz1 - bz0;
+        const int nrt = nkx * BYe * BZe;  // box rows per x-tile: (x-tile, y, z) row tasks
         __syncthreads();  // the previous tile is done with LDS
-        // wave 0: the neighbour tiles' record ranges, slot headers and the
-        // rows of each that fall inside the box; meanwhile the brick is cleared
+        // Round trip 1: every load this tile needs except the L2 gradients,
+        // issued together.  Row task ri = (x-tile, box y, box z) follows from
+        // the geometry alone: record range of its tile, the row's particle and
+        // own-side bits and the particles before the row (emission slot).
+        unsigned r_beg[RT], r_end[RT], r_word[RT], r_pre[RT];
+        int r_cell[RT], r_lx0[RT], r_lx1[RT], r_xb[RT], r_row[RT];
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const int ri = (int)threadIdx.x + q * kSobBlock;
+            r_beg[q] = r_end[q] = r_word[q] = r_pre[q] = 0u;
+            r_cell[q] = r_lx0[q] = r_lx1[q] = r_xb[q] = r_row[q] = 0;
+            if (ri < nrt) {
+                const int kxi = ri % nkx, rest = ri / nkx;
+                const int y = by0 + rest % BYe, z = bz0 + rest / BYe;
+                const int kx = kx0 + kxi, ky = y / S::TY, kz = z / S::TZ;
+                const unsigned tile = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
+                const int row = (y - ky * S::TY) + S::TY * (z - kz * S::TZ);
+                const unsigned* sl = b.tslot + (size_t)tile * kSlotWords;
+                r_beg[q] = ts[tile];
+                r_end[q] = ts[tile + 1];
+                r_word[q] = sl[1 + row];
+                r_pre[q] = sl[1 + kSlotRows + row];
+                r_lx0[q] = max(bx0 - kx * S::TX, 0);
+                r_lx1[q] = min(bx1 - kx * S::TX, S::TX);
+                r_xb[q] = kx * S::TX - ox;  // box x of the tile row's first pixel (may be < 0)
+                r_row[q] = (y - oy) + S::BY * (z - oz);
+                r_cell[q] = r_xb[q] + S::SX * r_row[q];
+            }
+        }
+        // wave 0: label pairs of the neighbour tiles (slot headers) and the
+        // tile's own rows for the core list
+        unsigned hdr = 0u, nb_beg = 0u, nb_end = 0u, own_word = 0u, own_pre = 0u;
         if (threadIdx.x < 64) {
-            unsigned beg = 0, hdr = 0, nrow = 0, lxy = 0, lzr = 0, tile = 0;
-            bool has = false;
             if (lane < nnt) {
                 const int kx = kx0 + lane % nkx, ky = ky0 + (lane / nkx) % nky, kz = kz0 + lane / (nkx * nky);
-                tile = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
-                beg = ts[tile];
-                has = ts[tile + 1] > beg;
-                if (has)
-                    hdr = b.tslot[(size_t)tile * kSlotWords];
-                const int lx0 = max(bx0 - kx * S::TX, 0), lx1 = min(bx1 - kx * S::TX, S::TX);
-                const int ly0 = max(by0 - ky * S::TY, 0), ly1 = min(by1 - ky * S::TY, S::TY);
-                const int lz0 = max(bz0 - kz * S::TZ, 0), lz1 = min(bz1 - kz * S::TZ, S::TZ);
-                lxy = (unsigned)lx0 | ((unsigned)lx1 << 8) | ((unsigned)ly0 << 16) | ((unsigned)ly1 << 24);
-                lzr = (unsigned)lz0 | ((unsigned)lz1 << 8);
-                nrow = has ? (unsigned)((ly1 - ly0) * (lz1 - lz0)) : 0u;
+                const unsigned tile = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
+                nb_beg = ts[tile];
+                nb_end = ts[tile + 1];
+                hdr = b.tslot[(size_t)tile * kSlotWords];
             }
-            const unsigned own_hdr = __shfl(hdr, kown);
-            const bool bad = has && (hdr != own_hdr || (hdr & 0xffffu) == 0xffffu);
-            unsigned tot;
-            const unsigned rp = wave_excl_scan_u(nrow, tot);
-            const bool any_bad = __ballot(bad) != 0;  // whole wave votes
-            if (lane < nnt) {
-                s_beg[lane] = beg;
-                s_tile[lane] = tile;
-                s_lxy[lane] = lxy;
-                s_lz[lane] = lzr;
-                s_rpre[lane] = rp;
-            }
-            if (lane == 0) {
-                s_rpre[nnt] = tot;
-                s_mode = any_bad ? 1u : 0u;
-            }
-        }
-        for (int k = threadIdx.x; k < S::NCELL; k += kSobBlock) {
-            s_v[k] = make_float2(0.f, 0.f);
-            s_n[k] = 0u;
-        }
-        __syncthreads();
-        if (s_mode) {  // several label pairs around this tile: staged scan over records
-            sob_generic_tile(g, b, cur, in, out, t, lds);
-            continue;
-        }
-        // rows of the box: read the particle bits from the tiles' slots and
-        // scatter the L2 gradients of exactly the box's particles
-        const unsigned nrows = s_rpre[nnt];
-        int k = 0;  // neighbour tile of this thread's row (monotone)
-        for (unsigned ri = threadIdx.x; ri < nrows; ri += kSobBlock) {
-            while (s_rpre[k + 1] <= ri)
-                ++k;
-            const unsigned i = ri - s_rpre[k];
-            const unsigned lxy = s_lxy[k], lzr = s_lz[k];
-            const int lx0 = lxy & 0xff, lx1 = (lxy >> 8) & 0xff, ly0 = (lxy >> 16) & 0xff, ly1 = lxy >> 24;
-            const int ny = ly1 - ly0;
-            const int ly = ly0 + (int)(i % (unsigned)ny), lz = (int)(lzr & 0xff) + (int)(i / (unsigned)ny);
-            const int row = ly + S::TY * lz;
-            const unsigned* sl = b.tslot + (size_t)s_tile[k] * kSlotWords;
-            const unsigned word = sl[1 + row], pre = sl[1 + kSlotRows + row];
-            const unsigned xm = ((1u << lx1) - 1u) & ~((1u << lx0) - 1u);
-            const unsigned pbits = word & 0xffffu, own = word >> 16;
-            const unsigned bits = pbits & xm;
-            unsigned idx = s_beg[k] + pre + (unsigned)__popc(pbits & ((1u << lx0) - 1u));
-            const int kx = (int)(s_tile[k] % (unsigned)g.ntx);
-            const int cbase = (kx * S::TX - ox) + S::BX * ((ly + ((int)(s_tile[k] / (unsigned)g.ntx) % g.nty) * S::TY - oy) +
-                                                           S::BY * (lz + (int)(s_tile[k] / ((unsigned)g.ntx * (unsigned)g.nty)) * S::TZ - oz));
-            float v[S::TX];
-#pragma unroll
-            for (int lx = 0; lx < S::TX; ++lx) {
-                v[lx] = 0.f;
-                if ((bits >> lx) & 1u)
-                    v[lx] = in[idx++];
-            }
-#pragma unroll
-            for (int lx = 0; lx < S::TX; ++lx) {
-                if ((bits >> lx) & 1u) {
-                    const int c = cbase + lx;
-                    if ((own >> lx) & 1u) {
-                        s_v[c] = make_float2(v[lx], 0.f);
-                        s_n[c] = 1u;
-                    } else {
-                        s_v[c] = make_float2(0.f, v[lx]);
-                        s_n[c] = 1u << 16;
-                    }
-                }
-            }
-        }
-        // the tile's own particles, in record order, as (brick corner cell, side)
-        if (threadIdx.x < 64) {
-            const unsigned* sl = b.tslot + (size_t)t * kSlotWords;
-            unsigned word = 0, pre = 0;
             if (lane < S::TY * S::TZ) {
-                word = sl[1 + lane];
-                pre = sl[1 + kSlotRows + lane];
+                const unsigned* sl = b.tslot + (size_t)t * kSlotWords;
+                own_word = sl[1 + lane];
+                own_pre = sl[1 + kSlotRows + lane];
             }
-            unsigned pbits = word & 0xffffu;
-            const unsigned own = word >> 16;
-            const int ly = lane & (S::TY - 1), lz = lane / S::TY;
+        }
+        // meanwhile: clear the brick and the row masks
+        for (int k = threadIdx.x; k < S::NCELL; k += kSobBlock)
+            s_v[k] = make_float2(0.f, 0.f);
+        for (int k = threadIdx.x; k < NROWS; k += kSobBlock)
+            s_m[k] = make_uint2(0u, 0u);
+        if (threadIdx.x < 64) {
+            // several label pairs around this tile: the staged generic scan
+            const unsigned own_hdr = __shfl(hdr, kown);
+            const bool has = nb_end > nb_beg;
+            const bool bad = has && (hdr != own_hdr || (hdr & 0xffffu) == 0xffffu);
+            const bool any_bad = __ballot(bad) != 0;
+            const unsigned cs0 = __shfl(nb_beg, kown), ncore0 = __shfl(nb_end, kown) - cs0;
+            // the tile's own particles, in record order, as (brick corner cell, side)
+            unsigned pbits = own_word & 0xffffu;
+            const unsigned own = own_word >> 16;
+            const int ly = lane % S::TY, lz = lane / S::TY;
+            unsigned pre = own_pre;
+            const unsigned row0 = (unsigned)(ly + S::BY * lz);
             while (pbits) {
                 const int lx = __ffs(pbits) - 1;
                 pbits &= pbits - 1;
-                s_core[pre++] = (unsigned)(lx + S::BX * (ly + S::BY * lz)) | (((own >> lx) & 1u) << 31);
+                s_core[pre++] = (unsigned)(lx + S::SX * (ly + S::BY * lz)) | ((unsigned)lx << 12) | (row0 << 17) |
+                                (((own >> lx) & 1u) << 31);
             }
-            if (lane == 0)
-                s_ncore = ts[t + 1] - ts[t];
+            if (lane == 0) {
+                s_mode = any_bad ? 1u : 0u;
+                s_ncore = ncore0;
+                s_cs = cs0;
+            }
         }
         __syncthreads();
-        const unsigned cs = ts[t], ncore = s_ncore;
+        if (s_mode) {
+            sob_generic_tile(g, b, cur, in, out, t, lds);
+            continue;
+        }
+        // Round trip 2: exactly the box's L2 gradients, scattered into the brick
+        float v[RT][S::TX];
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const unsigned pbits = r_word[q] & 0xffffu;
+            const unsigned xm = ((1u << r_lx1[q]) - 1u) & ~((1u << r_lx0[q]) - 1u);
+            const unsigned bits = r_end[q] > r_beg[q] ? (pbits & xm) : 0u;
+            unsigned idx = r_beg[q] + r_pre[q] + (unsigned)__popc(pbits & ((1u << r_lx0[q]) - 1u));
+#pragma unroll
+            for (int lx = 0; lx < S::TX; ++lx) {
+                v[q][lx] = 0.f;
+                if ((bits >> lx) & 1u)
+                    v[q][lx] = in[idx++];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            const unsigned pbits = r_word[q] & 0xffffu, own = r_word[q] >> 16;
+            const unsigned xm = ((1u << r_lx1[q]) - 1u) & ~((1u << r_lx0[q]) - 1u);
+            const unsigned bits = r_end[q] > r_beg[q] ? (pbits & xm) : 0u;
+#pragma unroll
+            for (int lx = 0; lx < S::TX; ++lx) {
+                if ((bits >> lx) & 1u) {
+                    const int c = r_cell[q] + lx;
+                    s_v[c] = ((own >> lx) & 1u) ? make_float2(v[q][lx], 0.f) : make_float2(0.f, v[q][lx]);
+                }
+            }
+            if (bits) {  // this tile row's particles in the box row's side masks
+                const int xb = r_xb[q];
+                const unsigned ma = bits & own, mb = bits & ~own;
+                atomicOr(&s_m[r_row[q]].x, xb >= 0 ? ma << xb : ma >> -xb);
+                atomicOr(&s_m[r_row[q]].y, xb >= 0 ? mb << xb : mb >> -xb);
+            }
+        }
+        __syncthreads();
+        const unsigned cs = s_cs, ncore = s_ncore;
         for (unsigned e = threadIdx.x; e < ncore; e += kSobBlock) {
             const unsigned ce = s_core[e];
-            const int c0 = (int)(ce & 0x7fffffffu);
+            const int c0 = (int)(ce & 0xfffu), lx = (int)((ce >> 12) & 31u), row0 = (int)((ce >> 17) & 0x1ffu);
             const bool sideA = (ce >> 31) != 0;
             const float2* vb = s_v + c0;
-            const unsigned* nbp = s_n + c0;
             float sA = 0.f, sB = 0.f;
-            unsigned cnt = 0;
+            // taps in groups: the scheduler may not hoist every brick read
+            // ahead of the arithmetic (that costs registers, so occupancy)
 #pragma unroll
-            for (int q = 0; q < S::NT; ++q) {
-                const float2 cv = vb[taps.off[q]];
-                const float wk = sw.w[taps.d2[q]];
-                sA = fmaf(wk, cv.x, sA);
-                sB = fmaf(wk, cv.y, sB);
-                if (FULL)
-                    cnt += nbp[taps.off[q]];
-                else
-                    cnt += nbp[taps.off[q]] * sw.m[taps.d2[q]];
+            for (int q0 = 0; q0 < S::NT; q0 += kTapGroup) {
+#pragma unroll
+                for (int q = q0; q < (q0 + kTapGroup < S::NT ? q0 + kTapGroup : S::NT); ++q) {
+                    const float2 cv = vb[taps.off[q]];
+                    const float wk = sw.w[taps.d2[q]];
+                    sA = fmaf(wk, cv.x, sA);
+                    sB = fmaf(wk, cv.y, sB);
+                }
+                __asm__ volatile("" ::: "memory");  // no brick read moves across a group
             }
+            // |Q_p| and |Q'_p|: particles of each side in the support, a window
+            // of every support row's side masks
+            unsigned nA = 0u, nB = 0u;
+#pragma unroll
+            for (int dz = -S::HZ; dz <= S::HZ; ++dz)
+#pragma unroll
+                for (int dy = -H; dy <= H; ++dy) {
+                    // a row outside the support (w < 0) gets an empty window: no branch,
+                    // so the row reads of one particle issue together
+                    const int w = sw.rw[(dy + H) + (2 * H + 1) * (dz + S::HZ)];
+                    const unsigned wm = w >= 0 ? (2u << (2 * w)) - 1u : 0u;
+                    const uint2 m = s_m[row0 + (dy + H) + S::BY * (dz + S::HZ)];
+                    const unsigned win = wm << (lx + H - (w >= 0 ? w : 0));
+                    nA += (unsigned)__popc(m.x & win);
+                    nB += (unsigned)__popc(m.y & win);
+                }
             const float same = sideA ? sA : sB, other = sideA ? sB : sA;
-            const unsigned nS = sideA ? (cnt & 0xffffu) : (cnt >> 16), nO = sideA ? (cnt >> 16) : (cnt & 0xffffu);
+            const unsigned nS = sideA ? nA : nB, nO = sideA ? nB : nA;
             float res = same / (float)nS;
             if (nO)
                 res -= other / (float)nO;
@@ -2174,6 +2222,7 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
     }
     hipLaunchKernelGGL(kb_flip, persistent_grid(totals[kPhPart]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
                        flags);
+    const unsigned nsc = totals[kPhScan] < 256u ? (totals[kPhScan] ? totals[kPhScan] : 1u) : 256u;
     if (g0.ndim == 3) {
         hipLaunchKernelGGL(kb_count<3>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off,
                            ns);
@@ -2183,7 +2232,6 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
                            ns);
         hipLaunchKernelGGL(kb_count_list<2>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.off, ns);
     }
-    const unsigned nsc = totals[kPhScan] < 256u ? (totals[kPhScan] ? totals[kPhScan] : 1u) : 256u;
     hipLaunchKernelGGL(kb_scan, dim3(nsc), dim3(kScanThreads), 0, s, t.d, t.par, t.off, ns, tol, flags);
     hipLaunchKernelGGL(kb_write, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
                        flags);
