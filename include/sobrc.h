@@ -53,6 +53,13 @@ enum {
 };
 enum { SOBRC_F32 = 0, SOBRC_U16 = 1 };            /* image element type */
 enum { SOBRC_PC = 0, SOBRC_PS = 1 };              /* piecewise constant / smooth */
+/* Pixel noise of the likelihood (Methods, Eq. (11), noise independent per
+ * pixel).  GAUSS: energy (I - J)^2 per pixel, the PC move re-estimates both
+ * region means exactly.  POISSON: energy J - I log J (negative log-likelihood
+ * without log I!), a move evaluated with both expected intensities J held at
+ * their current values (region means for PC, local means for PS), J raised
+ * to at least 1e-6; intended for photon-count images (I >= 0). */
+enum { SOBRC_NOISE_GAUSS = 0, SOBRC_NOISE_POISSON = 1 };
 /* Gradient mode of step/run.  AUTO: Sobolev gradients until the contour
  * oscillates, L2-type gradients from then on (the paper's remark after
  * Eq. (6) and its Fig. 3 experiment; the detection rule is this library's,
@@ -70,6 +77,7 @@ typedef struct {
     double lambda;         /* prior weight of Eq. (10), >= 0 */
     int32_t max_labels;    /* labels lie in [0, max_labels), 2 <= max_labels <= 65535 */
     int64_t max_particles; /* particle capacity, 1 <= max_particles < 2^31 */
+    int32_t noise;         /* SOBRC_NOISE_GAUSS or SOBRC_NOISE_POISSON */
 } sobrc_params;
 
 typedef struct sobrc_ctx sobrc_ctx;

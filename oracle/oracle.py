@@ -16,6 +16,7 @@ SRC = os.path.join(HERE, "sobrc_oracle.c")
 LIB = os.path.join(HERE, "libsobrc_oracle.so")
 
 PC, PS = 0, 1
+GAUSS, POISSON = 0, 1
 MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 NEIGH_BRUTE, NEIGH_CELLS = 0, 1
 
@@ -25,7 +26,7 @@ class Params(C.Structure):
         ("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("model", C.c_int32), ("ps_radius", C.c_int32),
         ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
-        ("max_labels", C.c_int32), ("threads", C.c_int32),
+        ("max_labels", C.c_int32), ("threads", C.c_int32), ("noise", C.c_int32),
     ]
 
 
@@ -84,19 +85,19 @@ def _ptr(a):
 
 
 def make_params(shape, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0, max_labels=2,
-                threads=1) -> Params:
+                threads=1, noise=GAUSS) -> Params:
     if len(shape) == 2:
         ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
     else:
         ndim, (nz, ny, nx) = 3, shape
     return Params(ndim, nx, ny, nz, model, ps_radius, float(E), float(eps), float(lam),
-                  max_labels, threads)
+                  max_labels, threads, noise)
 
 
 def params_of(w, threads=1) -> Params:
     """Parameters of a workloads.Workload."""
     return make_params(w.image.shape, w.E, w.lam, w.model, w.ps_radius, w.eps,
-                       w.max_labels, threads)
+                       w.max_labels, threads, getattr(w, "noise", GAUSS))
 
 
 def _img(I):

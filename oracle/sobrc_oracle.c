@@ -22,6 +22,9 @@
  *  - piecewise-constant data term: exact change of sum (I - mu)^2 when one pixel
  *    moves, with both region means re-estimated (theta_i = region mean);
  *  - piecewise-smooth data term: local means over a closed ball of radius R;
+ *  - Poisson noise (ORA_POISSON): pixel energy J - I log J; a move changes it
+ *    with both expected intensities held at their current values (region
+ *    means for PC, local means for PS), means below 1e-6 raised to 1e-6;
  *  - length prior: number of face-adjacent pixel pairs with different labels;
  *  - acceptance: every particle with gradient < 0 is a candidate, per pixel the
  *    smallest gradient wins (ties: smaller target label), all chosen moves are
@@ -165,6 +168,16 @@ static int face_count(const ora_params* P, const int32_t* L, int x, int y, int z
  * perturbed and the original contour (Eq. (11)), with the energy
  * E_ext + lambda E_int of Eq. (10), i.i.d. Gaussian pixel noise (squared
  * residuals) and a contour-length prior. */
+/* Poisson pixel energy J - v log J (Methods: negative log-likelihood of
+ * independent Poisson noise, constant log v! dropped) of a move from an
+ * expected intensity m_a to m_b, both held at their current values. */
+static double poisson_move(double v, double m_a, double m_b)
+{
+    double ja = m_a > ORA_POISSON_MIN_MEAN ? m_a : ORA_POISSON_MIN_MEAN;
+    double jb = m_b > ORA_POISSON_MIN_MEAN ? m_b : ORA_POISSON_MIN_MEAN;
+    return (jb - v * log(jb)) - (ja - v * log(ja));
+}
+
 void ora_l2diff(const ora_params* P, const double* I, const int32_t* L,
                 int64_t np, const int64_t* lin, const int32_t* a, const int32_t* b,
                 double* dE)
@@ -189,11 +202,15 @@ void ora_l2diff(const ora_params* P, const double* I, const int32_t* L,
              * (n_a pixels) and joins region b (n_b pixels), means re-estimated */
             double mu_a = s1[la] / (double)n[la];
             double mu_b = s1[lb] / (double)n[lb];
-            double gain_b = (double)n[lb] / ((double)n[lb] + 1.0) * (v - mu_b) * (v - mu_b);
-            double loss_a = 0.0;
-            if (n[la] > 1)
-                loss_a = (double)n[la] / ((double)n[la] - 1.0) * (v - mu_a) * (v - mu_a);
-            d_ext = gain_b - loss_a;
+            if (P->noise == ORA_POISSON) {
+                d_ext = poisson_move(v, mu_a, mu_b);
+            } else {
+                double gain_b = (double)n[lb] / ((double)n[lb] + 1.0) * (v - mu_b) * (v - mu_b);
+                double loss_a = 0.0;
+                if (n[la] > 1)
+                    loss_a = (double)n[la] / ((double)n[la] - 1.0) * (v - mu_a) * (v - mu_a);
+                d_ext = gain_b - loss_a;
+            }
         } else {
             /* local means over the closed ball |y - x|^2 <= R^2, per label */
             double sa = 0.0, sb = 0.0;
@@ -218,7 +235,10 @@ void ora_l2diff(const ora_params* P, const double* I, const int32_t* L,
                     }
             double m_a = sa / (double)ca;
             double m_b = sb / (double)cb;
-            d_ext = (v - m_b) * (v - m_b) - (v - m_a) * (v - m_a);
+            if (P->noise == ORA_POISSON)
+                d_ext = poisson_move(v, m_a, m_b);
+            else
+                d_ext = (v - m_b) * (v - m_b) - (v - m_a) * (v - m_a);
         }
         /* contour length: unlike face pairs at x change by c_a - c_b */
         double d_int = (double)(face_count(P, L, x, y, z, la) - face_count(P, L, x, y, z, lb));

@@ -32,7 +32,14 @@ typedef struct {
     double E, eps, lambda;     /* Sobolev length scale, smoothness, prior weight */
     int32_t max_labels;
     int32_t threads;           /* OpenMP threads for per-particle loops (<=1: serial) */
+    int32_t noise;             /* ORA_GAUSS or ORA_POISSON pixel noise */
 } ora_params;
+
+/* Pixel noise of the likelihood (Methods, Eq. (11) with independent noise):
+ * Gaussian -- energy (I - J)^2 per pixel; Poisson -- energy J - I log J (the
+ * negative log-likelihood without the constant log I!). */
+enum { ORA_GAUSS = 0, ORA_POISSON = 1 };
+#define ORA_POISSON_MIN_MEAN 1e-6 /* expected intensities below are raised to it */
 
 /* Sobolev kernel of Eq. (5); zero outside its support |r| <= E/2. */
 double ora_kernel(double r, double E, double eps);

@@ -57,6 +57,8 @@ int32_t validate(const sobrc_params* p)
         return fail(SOBRC_EINVAL, "image_dtype must be SOBRC_F32 or SOBRC_U16");
     if (p->model != SOBRC_PC && p->model != SOBRC_PS)
         return fail(SOBRC_EINVAL, "model must be SOBRC_PC or SOBRC_PS");
+    if (p->noise != SOBRC_NOISE_GAUSS && p->noise != SOBRC_NOISE_POISSON)
+        return fail(SOBRC_EINVAL, "noise must be SOBRC_NOISE_GAUSS or SOBRC_NOISE_POISSON");
     if (p->model == SOBRC_PS && (p->ps_radius < 2 || p->ps_radius > 32))
         return fail(SOBRC_EINVAL, "ps_radius must lie in [2, 32] (got %d)", p->ps_radius);
     if (!(p->E > 0.0 && p->E <= 64.0))
@@ -119,6 +121,7 @@ Geom make_geom(const sobrc_params* p)
     g.R = p->model == SOBRC_PS ? p->ps_radius : 0;
     g.R2 = g.R * g.R;
     g.model = p->model;
+    g.noise = p->noise;
     g.img_u16 = p->image_dtype == SOBRC_U16;
     g.lambda = (float)p->lambda;
     g.fx_scale = 1.0;

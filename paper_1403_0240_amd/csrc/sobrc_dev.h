@@ -71,6 +71,7 @@ struct Geom {
     int h;                      // largest axis offset k with k*k < T
     int R, R2;                  // PS ball radius and radius^2
     int model;                  // 0 PC, 1 PS
+    int noise;                  // 0 Gaussian, 1 Poisson pixel noise
     int img_u16;                // image element type
     float lambda;
     double fx_scale;            // fixed-point scale of intensity sums (2^s)

@@ -1105,6 +1105,14 @@ __device__ __forceinline__ void xcd_chunk(unsigned na, VB vb, unsigned& a0, unsi
 //   PC: n_b/(n_b+1) (v - mu_b)^2 - n_a/(n_a-1) (v - mu_a)^2   (means re-estimated)
 //   PS: (v - m_b(x))^2 - (v - m_a(x))^2, m_l = mean of label l in the ball |y-x| <= R
 //   + lambda (c_a - c_b), c_l = face neighbours with label l (contour length).
+// Poisson pixel energy J - v log J of a move from expected intensity m_a to
+// m_b, both held at their current values, J raised to at least 1e-6.
+__device__ __forceinline__ float poisson_move(float v, float m_a, float m_b)
+{
+    const float ja = fmaxf(m_a, 1e-6f), jb = fmaxf(m_b, 1e-6f);
+    return (jb - ja) - v * (logf(jb) - logf(ja));
+}
+
 __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const void* img, int cur, float* __restrict__ out, int gated, VB vb)
 {
     DevState* ds = b.ds;
@@ -1145,8 +1153,12 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
         float dext;
         if (g.model == 0) {
             float4 sa = b.lstat[a], sb = b.lstat[bl];
-            float da = v - sa.x, db = v - sb.x;
-            dext = sb.z * db * db - sa.y * da * da;
+            if (g.noise) {
+                dext = poisson_move(v, sa.x, sb.x);
+            } else {
+                float da = v - sa.x, db = v - sb.x;
+                dext = sb.z * db * db - sa.y * da * da;
+            }
         } else {
             float sa = 0.f, sb = 0.f;
             int na = 0, nb = 0;
@@ -1176,7 +1188,7 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
                 }
             }
             float ma = sa / (float)na, mb = sb / (float)nb;
-            dext = (v - mb) * (v - mb) - (v - ma) * (v - ma);
+            dext = g.noise ? poisson_move(v, ma, mb) : (v - mb) * (v - mb) - (v - ma) * (v - ma);
         }
         out[p] = dext + g.lambda * (float)(ca - cb);
     }

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsobrc.so
 OK, EINVAL, ECAPACITY, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 F32, U16 = 0, 1
 PC, PS = 0, 1
+NOISE_GAUSS, NOISE_POISSON = 0, 1
 MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE = range(6)
 KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write")
@@ -40,7 +41,7 @@ class Params(C.Structure):
         ("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("image_dtype", C.c_int32), ("model", C.c_int32), ("ps_radius", C.c_int32),
         ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
-        ("max_labels", C.c_int32), ("max_particles", C.c_int64),
+        ("max_labels", C.c_int32), ("max_particles", C.c_int64), ("noise", C.c_int32),
     ]
 
 
@@ -112,7 +113,7 @@ def _ptr(t):
 
 
 def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0,
-                max_labels=2, max_particles=1 << 20) -> Params:
+                max_labels=2, max_particles=1 << 20, noise=0) -> Params:
     """Parameters for an image of numpy-style shape (ny, nx) or (nz, ny, nx)."""
     if len(shape) == 2:
         ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
@@ -120,7 +121,7 @@ def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.
         ndim, (nz, ny, nx) = 3, shape
     dt = U16 if image_dtype in (torch.uint16, "uint16", U16) else F32
     return Params(ndim, nx, ny, nz, dt, model, ps_radius, float(E), float(eps), float(lam),
-                  max_labels, int(max_particles))
+                  max_labels, int(max_particles), int(noise))
 
 
 def workspace_size(params: Params) -> int:
@@ -314,7 +315,7 @@ def from_workload(w, max_particles=None, device="cuda"):
         max_particles = default_capacity(w.image.shape)
     dt = U16 if w.image.dtype == np.uint16 else F32
     p = make_params(w.image.shape, dt, w.E, w.lam, w.model, w.ps_radius, w.eps,
-                    w.max_labels, max_particles)
+                    w.max_labels, max_particles, getattr(w, "noise", 0))
     ctx = Context(p, device)
     if dt == U16:
         img = torch.from_numpy(np.ascontiguousarray(w.image, np.uint16)).to(device)

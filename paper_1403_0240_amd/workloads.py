@@ -33,6 +33,8 @@ import numpy as np
 
 PC = 0  # piecewise-constant image-generating function
 PS = 1  # piecewise-smooth image-generating function (local means)
+GAUSS = 0    # Gaussian pixel noise (squared residuals)
+POISSON = 1  # Poisson pixel noise (J - I log J)
 
 MODE_SOBOLEV = 0
 MODE_L2 = 1
@@ -51,6 +53,7 @@ class Workload:
     eps: float = 1.0 / 24.0
     iterations: int = 100
     max_labels: int = 2
+    noise: int = GAUSS
 
     @property
     def ndim(self) -> int:
@@ -185,12 +188,13 @@ def ellipsoids3d(seed: int = 2, n: int = 256, count: int = 25, fg: float = 800.0
 
 def random_multilabel(seed: int, shape, n_labels: int = 3, dtype=np.float32,
                       blobs: bool = True, E: float = 6.0, lam: float = 0.5,
-                      model: int = PC, ps_radius: int = 2) -> Workload:
+                      model: int = PC, ps_radius: int = 2, noise: int = GAUSS) -> Workload:
     """Small random image with several labels, for brute-force checks.
 
     With ``blobs`` the labels are a few random boxes (contours with both straight
     and corner pieces); without, every pixel gets an independent random label
-    (the worst case for several particles per pixel)."""
+    (the worst case for several particles per pixel).  With Poisson noise the
+    image holds photon counts with mean 4 + 6 * label (zero counts occur)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     if blobs:
         lab = np.zeros(shape, dtype=np.int32)
@@ -201,12 +205,14 @@ def random_multilabel(seed: int, shape, n_labels: int = 3, dtype=np.float32,
                 lab[tuple(slice(a, b) for a, b in zip(lo, hi))] = l
     else:
         lab = rng.integers(0, n_labels, size=shape).astype(np.int32)
-    if dtype == np.uint16:
+    if noise == POISSON:
+        img = rng.poisson(4.0 + 6.0 * lab.astype(np.float64)).astype(dtype)
+    elif dtype == np.uint16:
         img = rng.integers(0, 1000, size=shape).astype(np.uint16)
     else:
         img = (lab.astype(np.float64) * 0.7 + rng.normal(0.0, 0.4, size=shape)).astype(np.float32)
     return Workload(f"random_{'x'.join(map(str, shape))}_{seed}", img, lab, E=E, lam=lam,
-                    model=model, ps_radius=ps_radius, max_labels=n_labels)
+                    model=model, ps_radius=ps_radius, max_labels=n_labels, noise=noise)
 
 
 def half_plane(shape, cut: int, axis: int = 0, dtype=np.float32, E: float = 6.0) -> Workload:

@@ -44,7 +44,8 @@ def _p(**kw):
 @pytest.mark.parametrize("kw", [dict(ndim=4), dict(nx=0), dict(ny=40000), dict(nz=2),
                                 dict(image_dtype=7), dict(model=3), dict(model=S.PS, ps_radius=1),
                                 dict(E=0.0), dict(E=65.0), dict(eps=0.0), dict(lam=-1.0),
-                                dict(max_labels=1), dict(max_labels=65536), dict(max_particles=0)])
+                                dict(max_labels=1), dict(max_labels=65536), dict(max_particles=0),
+                                dict(noise=2), dict(noise=-1)])
 def test_bad_params(L, kw):
     n = C.c_size_t(0)
     assert L.workspace_size(C.byref(_p(**kw)), C.byref(n)) == S.EINVAL

@@ -96,6 +96,10 @@ CASES = {
     "disk2d_128": lambda: W.disk2d(),
     "half_plane_3d": lambda: W.half_plane((20, 21, 22), 9, axis=1, E=6.0),
     "wide_kernel_2d": lambda: W.random_multilabel(7, (70, 50), 2, E=40.0, lam=0.1),
+    "rand3d_poisson_pc": lambda: W.random_multilabel(22, (12, 13, 11), 3, dtype=np.uint16, E=6.0,
+                                                     lam=0.7, noise=W.POISSON),
+    "rand2d_poisson_ps": lambda: W.random_multilabel(23, (30, 34), 3, E=8.0, lam=0.5, model=W.PS,
+                                                     ps_radius=3, noise=W.POISSON),
 }
 
 

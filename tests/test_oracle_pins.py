@@ -468,3 +468,56 @@ def test_auto_mode_is_sobolev_then_l2(ora, case):
     assert expect_switch == s and expect_stop == auto["t"]
     assert why == ("tolerance" if case == "disk" else "cycle")
     assert np.array_equal(L, auto["L"])
+
+
+@pytest.mark.parametrize("model", ["pc", "ps"])
+def test_poisson_gradient_is_fixed_mean_energy_change(ora, model):
+    """Poisson noise (Methods: pixel energy J - I log J of independent Poisson
+    noise, log I! dropped): the oracle's L2 gradient of every particle equals
+    the change of the total energy sum_x (J(x) - I(x) log J(x)) when the
+    particle's pixel moves, with the expected intensities J held at the
+    current labels' values (region means, or local ball means), plus lambda
+    times the change of the face-pair count.  Computed here by brute force in
+    numpy; one region has zero counts so the 1e-6 floor of J is exercised."""
+    W_ = W.random_multilabel(21, (9, 10, 8), 3, E=6.0, lam=0.7,
+                             model=W.PC if model == "pc" else W.PS, ps_radius=2, noise=W.POISSON)
+    img = W_.image.astype(np.float64)
+    img[W_.labels == 2] = 0.0
+    P = ora.params_of(W_)
+    L = W_.labels
+    lin, a, b = ora.particles(P, L)
+    dE = ora.l2diff(P, img, L, lin, a, b)
+    nz, ny, nx = L.shape
+    Lf, If = L.reshape(-1), img.reshape(-1)
+
+    def expected(la, x, y, z):
+        if model == "pc":
+            m = If[Lf == la].mean() if (Lf == la).any() else 0.0
+        else:
+            s, c = 0.0, 0
+            for dz in range(-2, 3):
+                for dy in range(-2, 3):
+                    for dx in range(-2, 3):
+                        xx, yy, zz = x + dx, y + dy, z + dz
+                        if dx * dx + dy * dy + dz * dz <= 4 and 0 <= xx < nx and 0 <= yy < ny \
+                                and 0 <= zz < nz and L[zz, yy, xx] == la:
+                            s += img[zz, yy, xx]
+                            c += 1
+            m = s / c
+        return max(m, 1e-6)
+
+    def faces(x, y, z, l):
+        n = 0
+        for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            xx, yy, zz = x + dx, y + dy, z + dz
+            if 0 <= xx < nx and 0 <= yy < ny and 0 <= zz < nz and L[zz, yy, xx] == l:
+                n += 1
+        return n
+
+    for k in range(len(lin)):
+        x, y, z = lin[k] % nx, (lin[k] // nx) % ny, lin[k] // (nx * ny)
+        v = img[z, y, x]
+        ja, jb = expected(a[k], x, y, z), expected(b[k], x, y, z)
+        e_ext = (jb - v * np.log(jb)) - (ja - v * np.log(ja))
+        e_len = faces(x, y, z, a[k]) - faces(x, y, z, b[k])
+        assert dE[k] == pytest.approx(e_ext + 0.7 * e_len, rel=1e-12, abs=1e-9)
