@@ -19,6 +19,7 @@ PC, PS = 0, 1
 GAUSS, POISSON = 0, 1
 MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 NEIGH_BRUTE, NEIGH_CELLS = 0, 1
+TOPO_OFF, TOPO_SIMPLE = 0, 1
 
 
 class Params(C.Structure):
@@ -27,6 +28,7 @@ class Params(C.Structure):
         ("model", C.c_int32), ("ps_radius", C.c_int32),
         ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
         ("max_labels", C.c_int32), ("threads", C.c_int32), ("noise", C.c_int32),
+        ("topo", C.c_int32),
     ]
 
 
@@ -71,6 +73,11 @@ def lib():
                               C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ora_reversals.restype = C.c_int64
         L.ora_reversals.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        L.ora_simple.restype = C.c_int32
+        L.ora_simple.argtypes = [P(Params), C.c_void_p, C.c_int64, C.c_int32]
+        L.ora_accept_ranked.restype = C.c_int64
+        L.ora_accept_ranked.argtypes = [P(Params), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
         L.ora_energy_pc.restype = C.c_double
         L.ora_energy_pc.argtypes = [P(Params), C.c_void_p, C.c_void_p]
         L.ora_conv_closed_curve.restype = None
@@ -85,19 +92,20 @@ def _ptr(a):
 
 
 def make_params(shape, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0, max_labels=2,
-                threads=1, noise=GAUSS) -> Params:
+                threads=1, noise=GAUSS, topo=TOPO_OFF) -> Params:
     if len(shape) == 2:
         ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
     else:
         ndim, (nz, ny, nx) = 3, shape
     return Params(ndim, nx, ny, nz, model, ps_radius, float(E), float(eps), float(lam),
-                  max_labels, threads, noise)
+                  max_labels, threads, noise, topo)
 
 
 def params_of(w, threads=1) -> Params:
     """Parameters of a workloads.Workload."""
     return make_params(w.image.shape, w.E, w.lam, w.model, w.ps_radius, w.eps,
-                       w.max_labels, threads, getattr(w, "noise", GAUSS))
+                       w.max_labels, threads, getattr(w, "noise", GAUSS),
+                       getattr(w, "topo", TOPO_OFF))
 
 
 def _img(I):
@@ -198,6 +206,25 @@ def run_ex(P: Params, I, L, mode=MODE_SOBOLEV, max_iters=100, tol=0.0):
 def run(P: Params, I, L, mode=MODE_SOBOLEV, max_iters=100, tol=0.0):
     r = run_ex(P, I, L, mode, max_iters, tol)
     return r["L"], r["t"], r["n"], r["flips"]
+
+
+def simple(P: Params, L, i, label) -> bool:
+    """Is pixel i (linear index) a simple point of {L == label}?"""
+    L = _lab(L)
+    return bool(lib().ora_simple(C.byref(P), _ptr(L), int(i), int(label)))
+
+
+def accept_ranked(P: Params, L, lin, a, b, g, topo=TOPO_SIMPLE):
+    """Ranked acceptance on a copy of L.  Returns (L_next, executed mask, moves)."""
+    L = _lab(L).copy()
+    lin = np.ascontiguousarray(lin, np.int64)
+    a = np.ascontiguousarray(a, np.int32)
+    b = np.ascontiguousarray(b, np.int32)
+    g = np.ascontiguousarray(g, np.float64)
+    done = np.zeros(len(lin), np.uint8)
+    m = lib().ora_accept_ranked(C.byref(P), _ptr(L), len(lin), _ptr(lin), _ptr(a), _ptr(b),
+                                _ptr(g), int(topo), _ptr(done))
+    return L, done.astype(bool), m
 
 
 def reversals(L_prev, L_next, stamp, t):

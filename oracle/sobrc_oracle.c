@@ -29,6 +29,10 @@
  *  - acceptance: every particle with gradient < 0 is a candidate, per pixel the
  *    smallest gradient wins (ties: smaller target label), all chosen moves are
  *    applied together (no topology control);
+ *  - topological control (ORA_TOPO_SIMPLE): candidates ranked by (gradient,
+ *    pixel, target label) and executed in that order; a move runs only if
+ *    its pixel is a simple point (26/6 connectivity, 8/4 in 2D) of both
+ *    foreground regions it touches; background (label 0) is not controlled;
  *  - oscillation (AUTO mode): an iteration oscillates when at least half of
  *    its flips revert pixels that changed in the iteration before; after two
  *    oscillating iterations in a row, L2-type gradients are used from the
@@ -347,6 +351,138 @@ void ora_sobolev(const ora_params* P, int64_t np, const int64_t* lin,
     free(Z);
 }
 
+/* --- topological control ------------------------------------------------- */
+
+/* Membership of the 3x3(x3) neighbourhood of pixel i in {L == l}; index
+ * (dx+1) + 3(dy+1) + 9(dz+1), centre left out (0).  Outside the image: 0. */
+static void neighbourhood(const ora_params* P, const int32_t* L, int64_t i, int32_t l, int in[27])
+{
+    int x, y, z;
+    coords_of(P, i, &x, &y, &z);
+    int dz0 = P->ndim == 3 ? -1 : 0, dz1 = P->ndim == 3 ? 1 : 0;
+    for (int k = 0; k < 27; ++k)
+        in[k] = 0;
+    for (int dz = dz0; dz <= dz1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0)
+                    continue;
+                int k = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+                in[k] = in_bounds(P, x + dx, y + dy, z + dz) && L[lin_of(P, x + dx, y + dy, z + dz)] == l;
+            }
+}
+
+/* Number of connected components among the cells k with sel[k] set, where
+ * two cells are adjacent when their offsets differ by at most 1 in every
+ * axis (full = 1) or by 1 in exactly one axis (full = 0).  Only components
+ * holding a cell with need[k] set are counted (need = NULL: all). */
+static int components(const int sel[27], int full, const int* need)
+{
+    int comp[27], stack[27], count = 0;
+    for (int k = 0; k < 27; ++k)
+        comp[k] = -1;
+    for (int s0 = 0; s0 < 27; ++s0) {
+        if (!sel[s0] || comp[s0] >= 0)
+            continue;
+        int top = 0, hit = 0;
+        stack[top++] = s0;
+        comp[s0] = s0;
+        while (top > 0) {
+            int k = stack[--top];
+            if (!need || need[k])
+                hit = 1;
+            int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+            for (int j = 0; j < 27; ++j) {
+                if (!sel[j] || comp[j] >= 0)
+                    continue;
+                int ax = abs(j % 3 - kx), ay = abs((j / 3) % 3 - ky), az = abs(j / 9 - kz);
+                int adj = full ? (ax <= 1 && ay <= 1 && az <= 1) : (ax + ay + az == 1);
+                if (adj) {
+                    comp[j] = s0;
+                    stack[top++] = j;
+                }
+            }
+        }
+        count += hit;
+    }
+    return count;
+}
+
+int32_t ora_simple(const ora_params* P, const int32_t* L, int64_t i, int32_t l)
+{
+    int in[27], fg[27], bg[27], face[27];
+    neighbourhood(P, L, i, l, in);
+    const int three = P->ndim == 3;
+    for (int k = 0; k < 27; ++k) {
+        int ax = abs(k % 3 - 1), ay = abs((k / 3) % 3 - 1), az = abs(k / 9 - 1);
+        int cells = ax + ay + az;       /* 0 centre, 1 face, 2 edge, 3 corner */
+        int present = three || az == 0; /* 2D: the middle plane only */
+        fg[k] = present && cells > 0 && in[k];
+        /* complement: 18-neighbourhood in 3D (no corners), 8 in 2D */
+        bg[k] = present && cells > 0 && (three ? cells < 3 : 1) && !in[k];
+        face[k] = cells == 1;
+    }
+    int t_fg = components(fg, 1, NULL);
+    int t_bg = components(bg, 0, face);
+    return t_fg == 1 && t_bg == 1;
+}
+
+typedef struct {
+    double g;
+    int64_t i;
+    int32_t b;
+    int64_t k; /* particle index */
+} ora_cand;
+
+static int cand_cmp(const void* u, const void* v)
+{
+    const ora_cand* p = (const ora_cand*)u;
+    const ora_cand* q = (const ora_cand*)v;
+    if (p->g != q->g)
+        return p->g < q->g ? -1 : 1;
+    if (p->i != q->i)
+        return p->i < q->i ? -1 : 1;
+    return (p->b > q->b) - (p->b < q->b);
+}
+
+int64_t ora_accept_ranked(const ora_params* P, int32_t* L, int64_t np, const int64_t* lin,
+                          const int32_t* a, const int32_t* b, const double* g, int32_t topo,
+                          uint8_t* done)
+{
+    ora_cand* c = (ora_cand*)malloc(sizeof(ora_cand) * (size_t)(np > 0 ? np : 1));
+    int64_t nc = 0;
+    for (int64_t k = 0; k < np; ++k) {
+        if (done)
+            done[k] = 0;
+        if (g[k] < 0.0) {
+            c[nc].g = g[k];
+            c[nc].i = lin[k];
+            c[nc].b = b[k];
+            c[nc].k = k;
+            ++nc;
+        }
+    }
+    qsort(c, (size_t)nc, sizeof(ora_cand), cand_cmp);
+    int64_t moves = 0;
+    for (int64_t r = 0; r < nc; ++r) {
+        int64_t k = c[r].k, i = lin[k];
+        if (L[i] != a[k])
+            continue; /* the pixel already moved */
+        if (topo == ORA_TOPO_SIMPLE) {
+            if (a[k] >= 1 && !ora_simple(P, L, i, a[k]))
+                continue;
+            if (b[k] >= 1 && !ora_simple(P, L, i, b[k]))
+                continue;
+        }
+        L[i] = b[k];
+        if (done)
+            done[k] = 1;
+        ++moves;
+    }
+    free(c);
+    return moves;
+}
+
 /* --- one Region Competition iteration ------------------------------------ */
 
 int64_t ora_step(const ora_params* P, const double* I, int32_t* L, int32_t mode,
@@ -366,9 +502,13 @@ int64_t ora_step(const ora_params* P, const double* I, int32_t* L, int32_t mode,
     else
         memcpy(g1, g2, sizeof(double) * (size_t)np);
 
-    /* moves are decided from L_t only, then applied together */
     int64_t flips = 0;
     int64_t nvox = (int64_t)P->nx * P->ny * P->nz;
+    if (P->topo == ORA_TOPO_SIMPLE) {
+        flips = ora_accept_ranked(P, L, np, lin, a, b, g1, ORA_TOPO_SIMPLE, NULL);
+        goto out;
+    }
+    /* moves are decided from L_t only, then applied together */
     int32_t* Lnew = (int32_t*)malloc(sizeof(int32_t) * (size_t)nvox);
     memcpy(Lnew, L, sizeof(int32_t) * (size_t)nvox);
     for (int64_t k = 0; k < np;) {
@@ -388,6 +528,7 @@ int64_t ora_step(const ora_params* P, const double* I, int32_t* L, int32_t mode,
     memcpy(L, Lnew, sizeof(int32_t) * (size_t)nvox);
     free(Lnew);
 
+out:;
     int64_t ret = np;
     if (lin_o || a_o || b_o || dE_l2_o || dE_h1_o) {
         if (np > cap) {

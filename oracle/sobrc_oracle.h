@@ -33,7 +33,18 @@ typedef struct {
     int32_t max_labels;
     int32_t threads;           /* OpenMP threads for per-particle loops (<=1: serial) */
     int32_t noise;             /* ORA_GAUSS or ORA_POISSON pixel noise */
+    int32_t topo;              /* ORA_TOPO_OFF or ORA_TOPO_SIMPLE acceptance */
 } ora_params;
+
+/* Acceptance of the moves.  OFF: simultaneous, per pixel the smallest
+ * gradient.  SIMPLE: the moves are ranked by gradient (most negative first)
+ * and executed one after the other; a move runs only if its pixel still has
+ * the label it started from and is a simple point of the region it leaves and
+ * of the region it joins (labels >= 1; the background label 0 is not
+ * controlled), so no foreground region splits, merges, vanishes, or gains or
+ * loses a hole or tunnel (the topological control of Region Competition,
+ * Introduction, "The Region Competition (RC) algorithm"). */
+enum { ORA_TOPO_OFF = 0, ORA_TOPO_SIMPLE = 1 };
 
 /* Pixel noise of the likelihood (Methods, Eq. (11) with independent noise):
  * Gaussian -- energy (I - J)^2 per pixel; Poisson -- energy J - I log J (the
@@ -70,13 +81,37 @@ void ora_sobolev(const ora_params* P, int64_t np, const int64_t* lin,
                  double* out, int32_t neigh, int64_t nsel, const int64_t* sel);
 
 /* One Region Competition iteration on L (in place): particles, stats, L2
- * gradient, Sobolev smoothing (mode), simultaneous acceptance.  Optional
+ * gradient, Sobolev smoothing (mode), acceptance (simultaneous, or ranked
+ * with topological control when P->topo is ORA_TOPO_SIMPLE).  Optional
  * outputs (may be NULL, each needs cap entries): particle list and both
  * gradients.  Returns the particle count N_t (or -1 if N_t > cap while an
  * output array was requested); *nflips receives the number of changed pixels. */
 int64_t ora_step(const ora_params* P, const double* I, int32_t* L, int32_t mode,
                  int64_t cap, int64_t* lin, int32_t* a, int32_t* b,
                  double* dE_l2, double* dE_h1, int64_t* nflips);
+
+/* Digital topology (26/6 connectivity in 3D, 8/4 in 2D; pixels outside the
+ * image belong to no region).  Returns 1 if pixel i is a simple point of the
+ * set X = {L == l}: adding i to X (or removing it) leaves X's topology
+ * unchanged.  The label of i itself is ignored.  Test: the number of
+ * 26-components (8 in 2D) of X in the 26-neighbourhood of i is 1, and the
+ * number of 6-components (4 in 2D) of the complement within the
+ * 18-neighbourhood (8 in 2D) that touch a face neighbour of i is 1. */
+int32_t ora_simple(const ora_params* P, const int32_t* L, int64_t i, int32_t l);
+
+/* Ranked acceptance (Introduction, "The Region Competition (RC) algorithm":
+ * particles are ranked by energy difference before any move is executed, so
+ * the result does not depend on particle order; topological control keeps
+ * contours intact).  Candidates are the particles with g < 0, executed in
+ * order of (g, i, b) ascending on L in place; with topo = ORA_TOPO_SIMPLE a
+ * move of pixel i from a to b runs only if i still has label a, is simple
+ * for a (if a >= 1) and simple for b (if b >= 1).  Without topology control
+ * only the label check applies, which gives the simultaneous per-pixel rule.
+ * done (may be NULL, np entries) receives 1 for executed moves.  Returns the
+ * number of executed moves. */
+int64_t ora_accept_ranked(const ora_params* P, int32_t* L, int64_t np, const int64_t* lin,
+                          const int32_t* a, const int32_t* b, const double* g, int32_t topo,
+                          uint8_t* done);
 
 /* Oscillation test of one iteration.  A reversal is a pixel that changes
  * label in iteration t (L_prev -> L_next differ) and also changed in
