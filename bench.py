@@ -242,6 +242,8 @@ def parse():
                     help="time without per-kernel events (roofline omitted)")
     ap.add_argument("--requests", type=int, default=120, help="serving workload: request count")
     ap.add_argument("--hbm-gb", type=int, default=16, help="serving workload: HBM budget (GiB)")
+    ap.add_argument("--topo", action="store_true",
+                    help="ranked acceptance with topological control (simple points)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 256 MiB copy used to calibrate byte counters")
     return ap.parse_args()
@@ -292,6 +294,8 @@ def main():
     from paper_1403_0240_amd import workloads as W
 
     w = W.make(a.workload)
+    if a.topo:
+        w.topo = S.TOPO_SIMPLE
     ctx, img, lab = S.from_workload(w)
     S.init_labels(ctx, img, lab)
     n0 = S.particle_count(ctx)
@@ -342,6 +346,7 @@ def main():
         "config": {"workload": w.name, "shape": list(w.image.shape),
                    "image_dtype": str(w.image.dtype), "image_model": "piecewise-constant"
                    if w.model == W.PC else "piecewise-smooth", "E": w.E, "lambda": w.lam,
+                   "acceptance": "ranked, topology-controlled" if a.topo else "simultaneous",
                    "particles_init": n0, "particles_mean": updates / a.steps,
                    "flips_last": int(hf[-1]) if len(hf) else 0},
     }

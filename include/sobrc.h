@@ -48,7 +48,8 @@ enum {
     SOBRC_OK = 0,
     SOBRC_EINVAL = -1,     /* bad parameter, null pointer, label out of range */
     SOBRC_ECAPACITY = -2,  /* particle count would exceed max_particles */
-    SOBRC_EDEVICE = -3,    /* HIP runtime error (message kept in last_error) */
+    SOBRC_EDEVICE = -3,    /* HIP runtime error, or a ranked acceptance that did not finish
+                              within its pass limit (message kept in last_error) */
     SOBRC_ESTATE = -4      /* call order (e.g. step before init_labels) */
 };
 enum { SOBRC_F32 = 0, SOBRC_U16 = 1 };            /* image element type */
@@ -65,6 +66,22 @@ enum { SOBRC_NOISE_GAUSS = 0, SOBRC_NOISE_POISSON = 1 };
  * Eq. (6) and its Fig. 3 experiment; the detection rule is this library's,
  * see get_gradient_mode). */
 enum { SOBRC_MODE_SOBOLEV = 0, SOBRC_MODE_L2 = 1, SOBRC_MODE_AUTO = 2 };
+/* Acceptance of the moves (Introduction, "The Region Competition (RC)
+ * algorithm": moves are ranked by energy difference before they are executed,
+ * so the result does not depend on particle order, and topological control
+ * keeps contours intact).  OFF: every particle with gradient < 0 is a
+ * candidate, per pixel the smallest gradient wins (ties: smaller b), all
+ * chosen moves are applied together.  SIMPLE: the candidates run one after
+ * the other in order of (gradient, pixel linear index, b); a move runs only
+ * if its pixel still has the label it started from and is a simple point
+ * (26/6 connectivity in 3D, 8/4 in 2D; pixels outside the image belong to no
+ * region) of the region it leaves and of the region it joins, for labels >= 1
+ * (the background label 0 is not controlled).  No foreground region then
+ * splits, merges with another piece of itself, vanishes, or gains or loses a
+ * hole or tunnel.  The device reproduces the sequential order exactly.
+ * Contexts with SIMPLE take 8 bytes per pixel and 1 per particle more
+ * workspace and are not batched. */
+enum { SOBRC_TOPO_OFF = 0, SOBRC_TOPO_SIMPLE = 1 };
 
 typedef struct {
     int32_t ndim;          /* 2 or 3 */
@@ -78,6 +95,7 @@ typedef struct {
     int32_t max_labels;    /* labels lie in [0, max_labels), 2 <= max_labels <= 65535 */
     int64_t max_particles; /* particle capacity, 1 <= max_particles < 2^31 */
     int32_t noise;         /* SOBRC_NOISE_GAUSS or SOBRC_NOISE_POISSON */
+    int32_t topo;          /* SOBRC_TOPO_OFF or SOBRC_TOPO_SIMPLE (acceptance, see below) */
 } sobrc_params;
 
 typedef struct sobrc_ctx sobrc_ctx;
@@ -125,15 +143,24 @@ int32_t compute_l2_diff(sobrc_ctx* ctx, float* d_dE_l2, void* stream);
 int32_t sobolev_smooth(sobrc_ctx* ctx, const float* d_dE_l2, float* d_dE_h1, void* stream);
 
 /* One iteration: L2 gradient, Sobolev update (mode SOBOLEV; mode AUTO until
- * it has switched) or none (mode L2), acceptance -- every particle with gradient < 0 is a candidate, per pixel the
- * smallest gradient wins (ties: smaller b), all chosen moves applied together
- * -- then region statistics and the particle set are brought up to date.
+ * it has switched) or none (mode L2), acceptance as params.topo says (see
+ * SOBRC_TOPO_*), then region statistics and the particle set are brought up
+ * to date.
  * If d_nflips != NULL the number of changed pixels is written there (device
  * int32).  Asynchronous, no host synchronisation.  If the new particle set
  * would exceed max_particles the step is rolled back on the device and the
  * context reports ECAPACITY from its next synchronising call (ctx_sync, run,
  * get_particles); further steps do nothing until a new init_labels. */
 int32_t step(sobrc_ctx* ctx, int32_t mode, int32_t* d_nflips, void* stream);
+
+/* One iteration with a caller-supplied gradient instead of the computed one:
+ * d_grad (fp32, device, one value per current particle in context order, as
+ * get_particles lists them) drives the acceptance (params.topo), then region
+ * statistics and the particle set are brought up to date as in step().  For
+ * gradients from another source (e.g. another energy) and for checking the
+ * acceptance on its own.  d_grad is read during the call's kernels only.
+ * Asynchronous; errors as step(). */
+int32_t step_with_gradient(sobrc_ctx* ctx, const float* d_grad, int32_t* d_nflips, void* stream);
 
 /* Up to max_iters iterations; stops after the first iteration t whose flip
  * count is below flip_tol * N_t (N_t = particles at the start of t; flip_tol
@@ -265,7 +292,7 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n,
  * SOBRC_K_* below), the summed milliseconds and launch count since the last
  * reset.  Kinds: */
 enum { SOBRC_K_L2DIFF = 0, SOBRC_K_SOBOLEV = 1, SOBRC_K_FLIP = 2, SOBRC_K_COUNT = 3,
-       SOBRC_K_SCAN = 4, SOBRC_K_WRITE = 5, SOBRC_K_NKINDS = 6 };
+       SOBRC_K_SCAN = 4, SOBRC_K_WRITE = 5, SOBRC_K_TOPO = 6, SOBRC_K_NKINDS = 7 };
 int32_t profile_enable(sobrc_ctx* ctx, int32_t on);
 int32_t profile_read(sobrc_ctx* ctx, double* h_ms, int64_t* h_launches, int32_t reset);
 

@@ -71,6 +71,8 @@ int32_t validate(const sobrc_params* p)
         return fail(SOBRC_EINVAL, "max_labels must lie in [2, 65535] (got %d)", p->max_labels);
     if (p->max_particles < 1 || p->max_particles > 0x7fffffffLL)
         return fail(SOBRC_EINVAL, "max_particles must lie in [1, 2^31-1]");
+    if (p->topo != SOBRC_TOPO_OFF && p->topo != SOBRC_TOPO_SIMPLE)
+        return fail(SOBRC_EINVAL, "topo must be SOBRC_TOPO_OFF or SOBRC_TOPO_SIMPLE");
     return SOBRC_OK;
 }
 
@@ -122,6 +124,7 @@ Geom make_geom(const sobrc_params* p)
     g.R2 = g.R * g.R;
     g.model = p->model;
     g.noise = p->noise;
+    g.topo = p->topo;
     g.img_u16 = p->image_dtype == SOBRC_U16;
     g.lambda = (float)p->lambda;
     g.fx_scale = 1.0;
@@ -173,7 +176,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t lab, fstamp, dcnt, dlist, dflat, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
-        part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, ds;
+        part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, tstate, tmark, tlist0, tlist1, pmap, ds;
     size_t total;
 };
 
@@ -215,6 +218,12 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     L.part_act = take((size_t)g.ge * 4);
     L.part_off = take((size_t)g.ge * 4);
     L.part_aoff = take((size_t)g.ge * 4);
+    const bool topo = p->topo != SOBRC_TOPO_OFF;  // buffers of the ranked acceptance
+    L.tstate = take(topo ? (size_t)cap : 0);
+    L.tmark = take(topo ? (size_t)g.ntiles * 4 : 0);
+    L.tlist0 = take(topo ? (size_t)g.ntiles * 4 : 0);
+    L.tlist1 = take(topo ? (size_t)g.ntiles * 4 : 0);
+    L.pmap = take(topo ? (size_t)nvox * 8 : 0);
     L.ds = take(sizeof(DevState));
     L.total = o;
     return L;
@@ -251,6 +260,11 @@ Bufs carve(const Layout& L, char* base, long long cap)
     b.part_act = (unsigned*)(base + L.part_act);
     b.part_off = (unsigned*)(base + L.part_off);
     b.part_aoff = (unsigned*)(base + L.part_aoff);
+    b.tstate = (unsigned char*)(base + L.tstate);
+    b.tmark = (unsigned*)(base + L.tmark);
+    b.tlist[0] = (unsigned*)(base + L.tlist0);
+    b.tlist[1] = (unsigned*)(base + L.tlist1);
+    b.pmap = (unsigned long long*)(base + L.pmap);
     b.ds = (DevState*)(base + L.ds);
     b.cap = (unsigned)cap;
     return b;
@@ -371,6 +385,8 @@ int32_t status_of(const DevState& h)
         return fail(SOBRC_ECAPACITY, "particle set needs %u entries, capacity exceeded", h.need);
     if (h.err & kErrLabel)
         return fail(SOBRC_EINVAL, "label outside [0, max_labels)");
+    if (h.err & kErrTopo)
+        return fail(SOBRC_EDEVICE, "ranked acceptance did not finish within %d passes", kTopoMaxPasses);
     return SOBRC_OK;
 }
 
@@ -392,6 +408,9 @@ int32_t launch_step(sobrc_ctx* c, int mode, int32_t* d_nflips, float tol, hipStr
                         [&] { return launch_sobolev(g, b, c->sw, cur, b.dE, b.gH1, flags, 1, s); }));
         grad = b.gH1;
     }
+    if (g.topo)
+        SOBRC_TRY(timed(c, SOBRC_K_TOPO, s, "k_topo",
+                        [&] { return launch_topo(g, b, cur, grad, b.dE, flags, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip",
                     [&] { return launch_flip(g, b, c->image, cur, grad, b.dE, flags, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_COUNT, s, "k_count", [&] { return launch_count(g, b, cur, 1, 0, s); }));
@@ -536,6 +555,11 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
     SOBRC_HIP(hipMemsetAsync(b.fstamp, 0, (size_t)g.nx * g.ny * g.nz * 4, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.part_cnt, 0, (size_t)g.ge * 4, s), "hipMemsetAsync");
     SOBRC_HIP(hipMemsetAsync(b.part_act, 0, (size_t)g.ge * 4, s), "hipMemsetAsync");
+    if (g.topo) {
+        const size_t nvox = (size_t)g.nx * g.ny * g.nz;
+        SOBRC_HIP(hipMemsetAsync(b.pmap, 0xFF, nvox * 8, s), "hipMemsetAsync");
+        SOBRC_HIP(hipMemsetAsync(b.tmark, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
+    }
     SOBRC_TRY(upload_tables(g, c->p.E, c->p.eps, b.W, &c->sw, s));
     SOBRC_HIP(launch_init_labels(g, b, d_labels, d_image, s), "k_init_labels");
     DevState h;
@@ -610,6 +634,34 @@ int32_t step(sobrc_ctx* c, int32_t mode, int32_t* d_nflips, void* stream)
     if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
         return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
     return launch_step(c, mode, d_nflips, 0.f, (hipStream_t)stream);
+}
+
+int32_t step_with_gradient(sobrc_ctx* c, const float* d_grad, int32_t* d_nflips, void* stream)
+{
+    if (!c)
+        return fail(SOBRC_EINVAL, "ctx is NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "step_with_gradient before init_labels");
+    if (c->batch)
+        return fail(SOBRC_ESTATE, "context is in a batch: step the batch");
+    if (!d_grad)
+        return fail(SOBRC_EINVAL, "gradient must be a device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const int cur = c->cur, nxt = 1 - cur;
+    const Geom& g = c->g;
+    const Bufs& b = c->b;
+    if (g.topo)
+        SOBRC_TRY(timed(c, SOBRC_K_TOPO, s, "k_topo",
+                        [&] { return launch_topo(g, b, cur, d_grad, d_grad, kGate, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_FLIP, s, "k_flip",
+                    [&] { return launch_flip(g, b, c->image, cur, d_grad, d_grad, kGate, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_COUNT, s, "k_count", [&] { return launch_count(g, b, cur, 1, 0, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_SCAN, s, "k_scan",
+                    [&] { return launch_scan(g, b, cur, nxt, 0, 0.f, d_nflips, kGate, s); }));
+    SOBRC_TRY(timed(c, SOBRC_K_WRITE, s, "k_write",
+                    [&] { return launch_write(g, b, c->image, cur, nxt, d_grad, d_grad, kGate, 0, s); }));
+    c->cur = nxt;
+    return SOBRC_OK;
 }
 
 int32_t run(sobrc_ctx* c, int32_t max_iters, double flip_tol, int32_t mode, int32_t* h_iters_done, void* stream)
@@ -992,6 +1044,8 @@ int32_t batch_set(sobrc_batch* B, int32_t slot, sobrc_ctx* c, void* stream)
     if (c) {
         if (!c->initialized)
             return fail(SOBRC_ESTATE, "context not initialised");
+        if (c->g.topo)
+            return fail(SOBRC_EINVAL, "contexts with topological control are not batched");
         if (c->batch && (c->batch != B || B->slot[slot] != c))
             return fail(SOBRC_ESTATE, "context is already in a batch slot");
         bool any = false;

@@ -59,6 +59,11 @@ struct SobW {
 constexpr unsigned kErrCapacity = 1u;
 constexpr unsigned kErrLabel = 2u;
 constexpr unsigned kErrInput = 4u;
+constexpr unsigned kErrTopo = 8u;  // ranked acceptance did not finish within kTopoMaxPasses
+
+// Parallel rounds of the ranked acceptance before one block finishes the rest.
+constexpr int kTopoRounds = 24;
+constexpr int kTopoMaxPasses = 4096;  // passes of the finishing block over the tiles left
 
 // Problem geometry and parameters, passed by value to every kernel.
 struct Geom {
@@ -86,6 +91,7 @@ struct Geom {
     int sob_lds;                // dynamic LDS bytes of the generic Sobolev kernel
     int sob_grid;               // blocks of the Sobolev kernels (multiple of 8)
     int dlistm;                 // dirty tiles go through a flat list balanced over all waves (ge <= kMaxGrid)
+    int topo;                   // ranked acceptance with topological control
 };
 
 // Device-resident control block of a context.
@@ -106,6 +112,7 @@ struct DevState {
                             // bit 2: every flip of the last committed step was a reversal
     unsigned switch_it;     // 1 + first iteration run with L2 gradients in auto mode, 0: none yet
     unsigned ndirty;        // dirty tiles of the running step (flat list, when listed)
+    unsigned topo_cnt[kTopoRounds + 1];  // ranked acceptance: tiles listed for each round
 };
 
 // A block's place in the work of one context: its index and the block count
@@ -118,6 +125,7 @@ struct VB {
 // Step-kernel flags: stop when the context has stopped (error or tolerance);
 // auto gradient mode (Sobolev until oscillation, then L2).
 constexpr int kGate = 1, kAuto = 2;
+
 
 // Device pointers of one context (all carved from the caller's workspace).
 struct Bufs {
@@ -146,6 +154,11 @@ struct Bufs {
     unsigned* part_act;      // non-empty tiles per emission block
     unsigned* part_off;      // exclusive prefix of part_cnt
     unsigned* part_aoff;     // exclusive prefix of part_act
+    // ranked acceptance with topological control (topo only)
+    unsigned char* tstate;   // per particle: 0 no candidate, 1 undecided, 2 executed, 3 refused
+    unsigned* tmark;         // per tile: odd stamp of the iteration that listed it
+    unsigned* tlist[2];      // tiles of the even / odd rounds
+    unsigned long long* pmap;  // per pixel: smallest undecided key << 16 | label (~0: no candidate)
     DevState* ds;
     unsigned cap;
 };
@@ -186,6 +199,8 @@ hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur,
                           float* out, int gated, int use_slots, hipStream_t s);
 hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,
                        const float* grad_l2, int flags, hipStream_t s);
+hipError_t launch_topo(const Geom& g, const Bufs& b, int cur, const float* grad, const float* grad_l2,
+                       int flags, hipStream_t s);
 hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, hipStream_t s);
 hipError_t launch_scan(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol,
                        int32_t* d_nflips, int gated, hipStream_t s);

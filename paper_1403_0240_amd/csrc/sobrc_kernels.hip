@@ -975,7 +975,15 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
             b.rec[nxt][i] = b.rec[cur][i];
             uint2 r;
             int bb = 0;
-            if (decide_move(b.rec[cur], grad, n, (unsigned)i, r, bb)) {
+            bool mv;
+            if (g.topo) {
+                r = b.rec[cur][i];
+                bb = (int)(r.y >> 16);
+                mv = b.tstate[i] == 2;
+            } else {
+                mv = decide_move(b.rec[cur], grad, n, (unsigned)i, r, bb);
+            }
+            if (mv) {
                 int x, y, z;
                 unpack(g, r.x, x, y, z);
                 long long lin = lin_of(g, x, y, z);
@@ -1654,6 +1662,8 @@ __device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const vo
         s_f = 0;
         s_rv = 0;
     }
+    if (g.topo && vb.id == 0 && threadIdx.x <= (unsigned)kTopoRounds)
+        ds->topo_cnt[threadIdx.x] = 0;  // the ranked acceptance of this step is done
     __syncthreads();
     const unsigned n = ds->n[cur];
     const unsigned epoch = ds->epoch, it = ds->iters;
@@ -1670,7 +1680,22 @@ __device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const vo
         int a = 0, bb = 0;
         if (p < p1) {
             uint2 r;
-            if (decide_move(rec, grad, n, p, r, bb)) {
+            bool mv;
+            if (g.topo) {
+                // decided by the ranked acceptance; its per-pixel words are cleared here
+                const unsigned char st = b.tstate[p];
+                r = rec[p];
+                bb = (int)(r.y >> 16);
+                mv = st == 2;
+                if (st != 0) {
+                    int xx, yy, zz;
+                    unpack(g, r.x, xx, yy, zz);
+                    b.pmap[lin_of(g, xx, yy, zz)] = ~0ull;
+                }
+            } else {
+                mv = decide_move(rec, grad, n, p, r, bb);
+            }
+            if (mv) {
                 f = true;
                 int x, y, z;
                 unpack(g, r.x, x, y, z);
@@ -1745,6 +1770,380 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
                                                 const float* __restrict__ grad_l2, int flags)
 {
     flip_body(g, b, img, cur, grad_sob, grad_l2, flags, VB{blockIdx.x, gridDim.x});
+}
+
+// ------------------------------------- ranked acceptance, topological control
+//
+// Candidates (gradient < 0) run in the order of (gradient, pixel, target
+// label); a move is executed only if its pixel still has the label it started
+// from and is a simple point of the foreground regions it leaves and joins
+// (26/6 connectivity, 8/4 in 2D; label 0 is not controlled).  The sequential
+// result is reproduced exactly in parallel: a candidate is decided as soon as
+// every candidate ranked before it within its 3x3(x3) neighbourhood has been
+// decided.  Its decision reads only labels of that neighbourhood, which are
+// final for it by then, and two candidates decided together never lie in each
+// other's neighbourhood.
+//
+// Per candidate pixel a word holds the smallest undecided key (orderable
+// gradient << 16 | target label) and the pixel's current label.  Each word is
+// a complete state of its pixel: when its key ranks after a candidate, its
+// label is final for that candidate, whenever it was read.  Each block stages
+// a tile with its one-pixel halo in LDS and decides, in local rounds, what its
+// staged words allow; round launches take the tiles with undecided candidates
+// left, and after kTopoRounds launches one block finishes the rest.
+
+constexpr unsigned long long kKeyInf = 0xFFFFFFFFFFFFull;  // 48-bit key of a pixel with no undecided candidate
+constexpr int kTopoBox = 1000;                            // 10^3 box (3D); 18^2 = 324 in 2D
+// per-iteration tile stamp, odd so that a cleared mark (0) never matches
+__device__ __forceinline__ unsigned topo_stamp(unsigned it) { return (it << 1) | 1u; }
+
+// gradients < 0: the more negative, the smaller the key; ties by target label
+__device__ __forceinline__ unsigned long long cand_key(float gv, int bb)
+{
+    return ((unsigned long long)(~__float_as_uint(gv)) << 16) | (unsigned)bb;
+}
+
+// 3x3(x3) neighbourhood as a bit set: bit k = (dx+1) + 3(dy+1) [+ 9(dz+1)]
+template <int ND>
+struct NbBits {
+    static constexpr int N = ND == 3 ? 27 : 9;
+    static constexpr int CENTRE = N / 2;
+    static constexpr unsigned ALL = (1u << N) - 1u;
+    static constexpr int dist(int k)  // number of non-zero offsets
+    {
+        return (k % 3 != 1) + ((k / 3) % 3 != 1) + (ND == 3 ? (k / 9 != 1) : 0);
+    }
+    static constexpr unsigned x_at(int xi)
+    {
+        unsigned m = 0;
+        for (int k = 0; k < N; ++k)
+            if (k % 3 == xi)
+                m |= 1u << k;
+        return m;
+    }
+    static constexpr unsigned y_at(int yi)
+    {
+        unsigned m = 0;
+        for (int k = 0; k < N; ++k)
+            if ((k / 3) % 3 == yi)
+                m |= 1u << k;
+        return m;
+    }
+    static constexpr unsigned faces()
+    {
+        unsigned m = 0;
+        for (int k = 0; k < N; ++k)
+            if (dist(k) == 1)
+                m |= 1u << k;
+        return m;
+    }
+    // where the complement is examined: 18-neighbourhood (3D), 8 (2D)
+    static constexpr unsigned bg_domain()
+    {
+        unsigned m = 0;
+        for (int k = 0; k < N; ++k)
+            if (dist(k) >= 1 && (ND == 2 || dist(k) <= 2))
+                m |= 1u << k;
+        return m;
+    }
+};
+
+// one step of growth under full (8/26) or face (4/6) adjacency
+template <int ND>
+__device__ __forceinline__ unsigned grow_full(unsigned s)
+{
+    using M = NbBits<ND>;
+    // each axis step keeps to the N bits: a bit shifted past the top would
+    // come back into range with the next axis' right shift
+    s = (s | ((s << 1) & ~M::x_at(0)) | ((s >> 1) & ~M::x_at(2))) & M::ALL;
+    s = (s | ((s << 3) & ~M::y_at(0)) | ((s >> 3) & ~M::y_at(2))) & M::ALL;
+    if (ND == 3)
+        s = (s | (s << 9) | (s >> 9)) & M::ALL;
+    return s;
+}
+
+template <int ND>
+__device__ __forceinline__ unsigned grow_face(unsigned s)
+{
+    using M = NbBits<ND>;
+    unsigned r = s | ((s << 1) & ~M::x_at(0)) | ((s >> 1) & ~M::x_at(2)) | ((s << 3) & ~M::y_at(0)) |
+                 ((s >> 3) & ~M::y_at(2));
+    if (ND == 3)
+        r |= (s << 9) | (s >> 9);
+    return r & M::ALL;
+}
+
+// Simple point: m = the neighbours (centre excluded) inside the region.  The
+// region's part of the neighbourhood is one full-adjacency component, and the
+// complement's face-adjacency components within the 18- (8-) neighbourhood
+// that touch a face neighbour are exactly one.
+template <int ND>
+__device__ __forceinline__ bool simple_point(unsigned m)
+{
+    using M = NbBits<ND>;
+    if (m == 0)
+        return false;
+    unsigned c = m & (0u - m), p;
+    do {
+        p = c;
+        c = grow_full<ND>(c) & m;
+    } while (c != p);
+    if (c != m)
+        return false;
+    const unsigned dom = ~m & M::bg_domain();
+    const unsigned f = dom & M::faces();
+    if (f == 0)
+        return false;
+    c = f & (0u - f);
+    do {
+        p = c;
+        c = grow_face<ND>(c) & dom;
+    } while (c != p);
+    return (f & ~c) == 0;
+}
+
+// Per-pixel words are read and written at device scope, so that blocks on
+// other XCDs see a word soon after it is stored.
+__device__ __forceinline__ unsigned long long word_load(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void word_store(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decide what can be decided of tile t from the per-pixel words of the tile
+// and its halo, in local rounds on LDS; the tile's own words are written
+// back.  Returns (block-uniform) whether undecided candidates remain.
+template <int ND>
+__device__ bool topo_tile(const Geom& g, const Bufs& b, int cur, unsigned t, const float* __restrict__ grad,
+                          unsigned long long* words, unsigned short* s_lab, unsigned long long* s_key)
+{
+    using M = NbBits<ND>;
+    const TileInfo ti = tile_info(g, t);
+    const int nbox = ti.BX * ti.BY * ti.BZ, BXY = ti.BX * ti.BY;
+    const int ox = ti.tx * ti.TX - 1, oy = ti.ty * ti.TY - 1, oz = ti.tz * ti.TZ - ti.hz;
+    for (int k = threadIdx.x; k < nbox; k += kBlock) {
+        const int bx = k % ti.BX, by = (k / ti.BX) % ti.BY, bz = k / BXY;
+        const int x = ox + bx, y = oy + by, z = oz + bz;
+        unsigned short l = kNone;
+        unsigned long long key = kKeyInf;
+        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
+            const long long i = lin_of(g, x, y, z);
+            const unsigned long long w = word_load(words + i);
+            l = (w & 0xFFFFu) != 0xFFFFu ? (unsigned short)(w & 0xFFFFu) : b.lab[i];
+            key = w >> 16;
+        }
+        s_lab[k] = l;
+        s_key[k] = key;
+    }
+    __syncthreads();
+    const unsigned r0 = b.tstart[cur][t], r1 = b.tstart[cur][t + 1];
+    const uint2* rec = b.rec[cur];
+    auto cell_of = [&](unsigned pos) {
+        int x, y, z;
+        unpack(g, pos, x, y, z);
+        return (x - ox) + ti.BX * ((y - oy) + ti.BY * (z - oz));
+    };
+    auto nb_off = [&](int k) {
+        return (k % 3 - 1) + ti.BX * ((k / 3) % 3 - 1) + (ND == 3 ? BXY * (k / 9 - 1) : 0);
+    };
+    // one undecided candidate: 0 while a candidate ranked before it is
+    // undecided within its neighbourhood, else 2 (executed) or 3 (refused)
+    auto decide = [&](unsigned rw, int c, unsigned long long kc) -> unsigned char {
+        if (s_key[c] != kc)
+            return 0;  // an undecided move of this pixel ranks first
+        const unsigned gc = (unsigned)(kc >> 16);
+        bool ready = true;  // all neighbours read: no branch per neighbour
+#pragma unroll
+        for (int k = 0; k < M::N; ++k) {
+            if (k == M::CENTRE)
+                continue;
+            const unsigned gy = (unsigned)(s_key[c + nb_off(k)] >> 16);
+            // a neighbour ranks first: smaller gradient, or equal and earlier in raster order
+            ready = ready && !(gy < gc || (gy == gc && k < M::CENTRE));
+        }
+        if (!ready)
+            return 0;
+        const int a = (int)(rw & 0xFFFFu), bb = (int)(rw >> 16);
+        bool ok = s_lab[c] == a;
+        if (ok) {
+            unsigned ma = 0, mb = 0;
+#pragma unroll
+            for (int k = 0; k < M::N; ++k) {
+                if (k == M::CENTRE)
+                    continue;
+                const unsigned short l = s_lab[c + nb_off(k)];
+                ma |= (unsigned)(l == a) << k;
+                mb |= (unsigned)(l == bb) << k;
+            }
+            ok = (a == 0 || simple_point<ND>(ma)) && (bb == 0 || simple_point<ND>(mb));
+        }
+        if (ok)
+            s_lab[c] = (unsigned short)bb;
+        return ok ? 2 : 3;
+    };
+    auto clear_own_keys = [&]() {
+        const int ntile = ti.TX * ti.TY * ti.TZ;
+        for (int k = threadIdx.x; k < ntile; k += kBlock) {
+            const int lx = k % ti.TX, ly = (k / ti.TX) % ti.TY, lz = k / (ti.TX * ti.TY);
+            s_key[(lx + 1) + ti.BX * ((ly + 1) + ti.BY * (lz + ti.hz))] = kKeyInf;
+        }
+    };
+    int pend = 0;
+    for (;;) {
+        int prog = 0;
+        for (unsigned p = r0 + threadIdx.x; p < r1; p += kBlock) {
+            if (b.tstate[p] != 1)
+                continue;
+            const uint2 r = rec[p];
+            const unsigned char d = decide(r.y, cell_of(r.x), cand_key(grad[p], (int)(r.y >> 16)));
+            if (d) {
+                b.tstate[p] = d;
+                prog = 1;
+            }
+        }
+        if (!__syncthreads_or(prog))
+            break;
+        clear_own_keys();
+        __syncthreads();
+        for (unsigned p = r0 + threadIdx.x; p < r1; p += kBlock)
+            if (b.tstate[p] == 1) {
+                const uint2 r = rec[p];
+                atomicMin(&s_key[cell_of(r.x)], cand_key(grad[p], (int)(r.y >> 16)));
+            }
+        __syncthreads();
+    }
+    for (unsigned p = r0 + threadIdx.x; p < r1; p += kBlock) {
+        const unsigned char st = b.tstate[p];
+        if (st == 0)
+            continue;
+        pend |= st == 1;
+        const uint2 r = rec[p];
+        const int c = cell_of(r.x);
+        int x, y, z;
+        unpack(g, r.x, x, y, z);
+        word_store(words + lin_of(g, x, y, z), (s_key[c] << 16) | s_lab[c]);
+    }
+    return __syncthreads_or(pend) != 0;
+}
+
+// Candidates of state t: state, per-pixel smallest key, and the list of tiles
+// holding candidates (round 0's work).
+__global__ __launch_bounds__(kBlock) void k_topo_prep(Geom g, Bufs b, int cur, const float* __restrict__ grad_sob,
+                                                     const float* __restrict__ grad_l2, int flags)
+{
+    DevState* ds = b.ds;
+    if (stopped(ds))
+        return;
+    const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
+    const unsigned n = ds->n[cur], stamp = topo_stamp(ds->iters);
+    unsigned p0, p1;
+    xcd_chunk(n, VB{blockIdx.x, gridDim.x}, p0, p1);
+    for (unsigned base = p0; base < p1; base += kBlock) {
+        const unsigned p = base + threadIdx.x;
+        unsigned tile = 0xFFFFFFFFu;
+        if (p < p1) {
+            const float gv = grad[p];
+            const bool cand = gv < 0.f;
+            b.tstate[p] = cand ? 1 : 0;
+            if (cand) {
+                const uint2 r = b.rec[cur][p];
+                int x, y, z;
+                unpack(g, r.x, x, y, z);
+                atomicMin(&b.pmap[lin_of(g, x, y, z)], (cand_key(gv, (int)(r.y >> 16)) << 16) | 0xFFFFull);
+                tile = (unsigned)((x >> g.tsx) + g.ntx * ((y >> g.tsy) + g.nty * (z >> g.tsz)));
+            }
+        }
+        // records are tile-sorted: the first candidate lane of each run of
+        // one tile lists it, the tile's stamp keeps it listed once
+        const unsigned prev = __shfl_up(tile, 1);
+        if (tile != 0xFFFFFFFFu && (lane_id() == 0 || prev != tile) && atomicExch(&b.tmark[tile], stamp) != stamp)
+            b.tlist[0][atomicAdd(&ds->topo_cnt[0], 1u)] = tile;
+    }
+}
+
+// Round r: the tiles listed by round r - 1 (by the preparation for r = 0);
+// those with undecided candidates left are listed for round r + 1.  The
+// per-pixel words are updated in place: a block may see a neighbour's words
+// from before or after that neighbour's work in this round, and either is a
+// valid state of those pixels for every decision taken from it.
+template <int ND>
+__global__ __launch_bounds__(kBlock) void k_topo_round(Geom g, Bufs b, int cur, const float* __restrict__ grad_sob,
+                                                      const float* __restrict__ grad_l2, int flags, int r)
+{
+    __shared__ unsigned short s_lab[kTopoBox];
+    __shared__ unsigned long long s_key[kTopoBox];
+    DevState* ds = b.ds;
+    if (stopped(ds))
+        return;
+    const unsigned n = ds->topo_cnt[r];
+    // consecutive list entries (neighbouring tiles, mostly) on one XCD
+    const unsigned G = gridDim.x;
+    const unsigned L = (G & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
+    if (L >= n)
+        return;
+    const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
+    const unsigned* list = b.tlist[r & 1];
+    unsigned* next = b.tlist[(r + 1) & 1];
+    for (unsigned i = L; i < n; i += G) {
+        const unsigned t = list[i];
+        const bool pend = topo_tile<ND>(g, b, cur, t, grad, b.pmap, s_lab, s_key);
+        if (pend && threadIdx.x == 0)
+            next[atomicAdd(&ds->topo_cnt[r + 1], 1u)] = t;
+        __syncthreads();  // LDS reuse by the next tile
+    }
+}
+
+// One block: the tiles left after the parallel rounds, until none has
+// undecided candidates.  Every pass decides at least the first-ranked
+// undecided candidate.
+template <int ND>
+__global__ __launch_bounds__(kBlock) void k_topo_finish(Geom g, Bufs b, int cur, const float* __restrict__ grad_sob,
+                                                       const float* __restrict__ grad_l2, int flags)
+{
+    __shared__ unsigned short s_lab[kTopoBox];
+    __shared__ unsigned long long s_key[kTopoBox];
+    __shared__ unsigned s_mk;
+    DevState* ds = b.ds;
+    if (stopped(ds))
+        return;
+    const unsigned nleft = ds->topo_cnt[kTopoRounds];
+    if (nleft == 0)
+        return;
+    const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
+    const unsigned done = topo_stamp(ds->iters) + 1u;  // even: never a stamp
+    const unsigned* list = b.tlist[kTopoRounds & 1];
+    for (int pass = 0;; ++pass) {
+        if (pass == kTopoMaxPasses) {
+            // a chain of dependent candidates across more tiles than this is
+            // not expected; report instead of running on
+            if (threadIdx.x == 0)
+                atomicOr(&ds->err, kErrTopo);
+            return;
+        }
+        bool any = false;
+        for (unsigned i = 0; i < nleft; ++i) {
+            const unsigned t = list[i];
+            if (threadIdx.x == 0)
+                s_mk = b.tmark[t];
+            __syncthreads();
+            const unsigned mk = s_mk;  // one value for the whole block
+            __syncthreads();
+            if (mk == done)
+                continue;
+            any = true;
+            const bool pend = topo_tile<ND>(g, b, cur, t, grad, b.pmap, s_lab, s_key);
+            __syncthreads();
+            if (threadIdx.x == 0 && !pend)
+                b.tmark[t] = done;
+            __syncthreads();
+        }
+        if (!any)
+            break;
+    }
 }
 
 // ------------------------------------------------------------- export / io
@@ -1931,6 +2330,26 @@ hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, c
                        const float* grad_l2, int flags, hipStream_t s)
 {
     hipLaunchKernelGGL(k_flip, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, grad, grad_l2, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_topo(const Geom& g, const Bufs& b, int cur, const float* grad, const float* grad_l2, int flags,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_topo_prep, dim3(g.gp), dim3(kBlock), 0, s, g, b, cur, grad, grad_l2, flags);
+    for (int r = 0; r < kTopoRounds; ++r) {
+        // later rounds have fewer tiles left: smaller grids (multiples of 8)
+        int G = g.sob_grid >> (r < 5 ? r : 5);
+        G = G < 8 ? 8 : (G + 7) / 8 * 8;
+        if (g.ndim == 3)
+            hipLaunchKernelGGL(k_topo_round<3>, dim3(G), dim3(kBlock), 0, s, g, b, cur, grad, grad_l2, flags, r);
+        else
+            hipLaunchKernelGGL(k_topo_round<2>, dim3(G), dim3(kBlock), 0, s, g, b, cur, grad, grad_l2, flags, r);
+    }
+    if (g.ndim == 3)
+        hipLaunchKernelGGL(k_topo_finish<3>, dim3(1), dim3(kBlock), 0, s, g, b, cur, grad, grad_l2, flags);
+    else
+        hipLaunchKernelGGL(k_topo_finish<2>, dim3(1), dim3(kBlock), 0, s, g, b, cur, grad, grad_l2, flags);
     return hipGetLastError();
 }
 

@@ -19,11 +19,12 @@ F32, U16 = 0, 1
 PC, PS = 0, 1
 NOISE_GAUSS, NOISE_POISSON = 0, 1
 MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
-K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE = range(6)
-KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write")
+TOPO_OFF, TOPO_SIMPLE = 0, 1
+K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE, K_TOPO = range(7)
+KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write", "k_topo")
 
 EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "compute_l2_diff",
-           "sobolev_smooth", "step", "run", "ctx_sync", "get_particles", "get_labels",
+           "sobolev_smooth", "step", "step_with_gradient", "run", "ctx_sync", "get_particles", "get_labels",
            "get_region_stats", "get_history", "get_gradient_mode", "sobolev_particles_workspace_size",
            "sobolev_smooth_particles", "profile_enable", "profile_read", "batch_workspace_size",
            "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_run",
@@ -42,6 +43,7 @@ class Params(C.Structure):
         ("image_dtype", C.c_int32), ("model", C.c_int32), ("ps_radius", C.c_int32),
         ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
         ("max_labels", C.c_int32), ("max_particles", C.c_int64), ("noise", C.c_int32),
+        ("topo", C.c_int32),
     ]
 
 
@@ -65,6 +67,7 @@ def lib():
         "compute_l2_diff": [V, V, V],
         "sobolev_smooth": [V, V, V, V],
         "step": [V, I32, V, V],
+        "step_with_gradient": [V, V, V, V],
         "run": [V, I32, C.c_double, I32, P(I32), V],
         "ctx_sync": [V, V],
         "get_particles": [V, P(I64), V, V, V, V],
@@ -113,7 +116,7 @@ def _ptr(t):
 
 
 def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0,
-                max_labels=2, max_particles=1 << 20, noise=0) -> Params:
+                max_labels=2, max_particles=1 << 20, noise=0, topo=TOPO_OFF) -> Params:
     """Parameters for an image of numpy-style shape (ny, nx) or (nz, ny, nx)."""
     if len(shape) == 2:
         ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
@@ -121,7 +124,7 @@ def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.
         ndim, (nz, ny, nx) = 3, shape
     dt = U16 if image_dtype in (torch.uint16, "uint16", U16) else F32
     return Params(ndim, nx, ny, nz, dt, model, ps_radius, float(E), float(eps), float(lam),
-                  max_labels, int(max_particles), int(noise))
+                  max_labels, int(max_particles), int(noise), int(topo))
 
 
 def workspace_size(params: Params) -> int:
@@ -214,6 +217,16 @@ def step(ctx: Context, mode=MODE_SOBOLEV, nflips: torch.Tensor | None = None, st
     _check(lib().step(ctx.handle, mode, _ptr(nflips), _stream(stream)))
 
 
+def step_with_gradient(ctx: Context, grad: torch.Tensor, nflips: torch.Tensor | None = None, stream=None):
+    """One iteration driven by a caller-supplied fp32 gradient (device tensor,
+    one value per current particle in context order)."""
+    if grad.dtype != torch.float32 or not grad.is_cuda or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous float32 device tensor")
+    if grad.numel() < particle_count(ctx, stream):
+        raise ValueError("grad needs one value per current particle")
+    _check(lib().step_with_gradient(ctx.handle, _ptr(grad), _ptr(nflips), _stream(stream)))
+
+
 def run(ctx: Context, max_iters: int, flip_tol: float = 0.0, mode=MODE_SOBOLEV, stream=None) -> int:
     done = C.c_int32(0)
     _check(lib().run(ctx.handle, max_iters, float(flip_tol), mode, C.byref(done), _stream(stream)))
@@ -301,11 +314,12 @@ def profile_enable(ctx: Context, on: bool = True):
 def profile_read(ctx: Context, reset: bool = True):
     """{kernel name: (total ms, launches)} since the last reset."""
     import numpy as np
-    ms = np.zeros(6, np.float64)
-    n = np.zeros(6, np.int64)
+    nk = len(KERNEL_NAMES)  # SOBRC_K_NKINDS
+    ms = np.zeros(nk, np.float64)
+    n = np.zeros(nk, np.int64)
     _check(lib().profile_read(ctx.handle, ms.ctypes.data_as(C.c_void_p),
                               n.ctypes.data_as(C.c_void_p), 1 if reset else 0))
-    return {KERNEL_NAMES[k]: (float(ms[k]), int(n[k])) for k in range(6)}
+    return {KERNEL_NAMES[k]: (float(ms[k]), int(n[k])) for k in range(nk)}
 
 
 def from_workload(w, max_particles=None, device="cuda"):
@@ -315,7 +329,7 @@ def from_workload(w, max_particles=None, device="cuda"):
         max_particles = default_capacity(w.image.shape)
     dt = U16 if w.image.dtype == np.uint16 else F32
     p = make_params(w.image.shape, dt, w.E, w.lam, w.model, w.ps_radius, w.eps,
-                    w.max_labels, max_particles, getattr(w, "noise", 0))
+                    w.max_labels, max_particles, getattr(w, "noise", 0), getattr(w, "topo", 0))
     ctx = Context(p, device)
     if dt == U16:
         img = torch.from_numpy(np.ascontiguousarray(w.image, np.uint16)).to(device)

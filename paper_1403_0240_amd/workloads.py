@@ -54,6 +54,7 @@ class Workload:
     iterations: int = 100
     max_labels: int = 2
     noise: int = GAUSS
+    topo: int = 0              # 1: ranked acceptance with topological control
 
     @property
     def ndim(self) -> int:

@@ -45,7 +45,7 @@ def _p(**kw):
                                 dict(image_dtype=7), dict(model=3), dict(model=S.PS, ps_radius=1),
                                 dict(E=0.0), dict(E=65.0), dict(eps=0.0), dict(lam=-1.0),
                                 dict(max_labels=1), dict(max_labels=65536), dict(max_particles=0),
-                                dict(noise=2), dict(noise=-1)])
+                                dict(noise=2), dict(noise=-1), dict(topo=2), dict(topo=-1)])
 def test_bad_params(L, kw):
     n = C.c_size_t(0)
     assert L.workspace_size(C.byref(_p(**kw)), C.byref(n)) == S.EINVAL
@@ -68,6 +68,15 @@ def test_workspace_grows_with_capacity(L):
     assert b.value - a.value >= 99000 * 23  # records x2, gradients x2
 
 
+def test_topology_workspace(L):
+    """Topological control adds an 8-byte word per pixel and a state byte
+    per particle (plus per-tile marks)."""
+    a, b = C.c_size_t(0), C.c_size_t(0)
+    assert L.workspace_size(C.byref(_p()), C.byref(a)) == 0
+    assert L.workspace_size(C.byref(_p(topo=S.TOPO_SIMPLE)), C.byref(b)) == 0
+    assert b.value - a.value >= 64 * 48 * 8 + 1000
+
+
 def test_call_order_and_nulls(L):
     p = _p()
     n = C.c_size_t(0)
@@ -80,6 +89,8 @@ def test_call_order_and_nulls(L):
     assert L.ctx_create(C.byref(p), fake, n.value, C.byref(h)) == S.OK
     try:
         assert L.step(h, S.MODE_SOBOLEV, None, None) == S.ESTATE
+        assert L.step_with_gradient(h, fake, None, None) == S.ESTATE
+        assert L.step_with_gradient(None, fake, None, None) == S.EINVAL
         assert L.run(h, 3, 0.0, S.MODE_SOBOLEV, None, None) == S.ESTATE
         assert L.compute_l2_diff(h, fake, None) == S.ESTATE
         assert L.sobolev_smooth(h, fake, fake, None) == S.ESTATE

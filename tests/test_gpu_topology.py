@@ -1,0 +1,264 @@
+"""Ranked acceptance with topological control on the GPU (params.topo =
+SIMPLE), through the C ABI, against the oracle.
+
+Bars:
+  * with a given gradient (step_with_gradient): labels, flip counts, region
+    statistics and the next particle set bit-exact.  The gradients come from
+    a seeded table over (pixel, target label), quantised to multiples of 1/32
+    so that many of them tie: the tie rule (pixel index, then target label)
+    is exercised, and fp32 holds every value exactly, so both sides rank the
+    same numbers;
+  * with the computed gradients (step/run): as the plain acceptance, labels
+    identical outside the margin; with ranking a decision is marginal when a
+    candidate of the pixel's 5x5(x5) neighbourhood has |g| <= 1e-4 max|g| or
+    two candidates within one pixel of each other there have gradients that
+    close;
+  * independent of the oracle: every foreground region keeps its topology
+    (components, complement components, Euler characteristic) over a run.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1403_0240_amd import sobrc as S  # noqa: E402
+from paper_1403_0240_amd import workloads as W  # noqa: E402
+from topo_invariants import topo  # noqa: E402
+
+MARGIN = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S.lib()
+
+
+def _with_topo(w, on=True):
+    w.topo = S.TOPO_SIMPLE if on else S.TOPO_OFF
+    return w
+
+
+def gpu_state(w, cap=None):
+    ctx, img, lab = S.from_workload(w, max_particles=cap)
+    S.init_labels(ctx, img, lab)
+    return ctx, img, lab
+
+
+def gpu_particles(ctx):
+    lin, a, b = (t.cpu().numpy() for t in S.get_particles(ctx))
+    return lin.astype(np.int64), a, b
+
+
+def _keys(lin, b):
+    return np.asarray(lin, np.int64) * 65536 + np.asarray(b, np.int64)
+
+
+def grad_table(seed, nvox, M):
+    """Seeded gradient per (pixel, target label): multiples of 1/32 in [-2, 1)."""
+    return np.random.default_rng(seed).integers(-64, 32, size=nvox * M).astype(np.float64) / 32.0
+
+
+EXACT = {
+    "blobs2d": lambda: W.random_multilabel(31, (45, 53), 3, E=6.0),
+    "noise2d_4": lambda: W.random_multilabel(32, (37, 41), 4, blobs=False, E=6.0),
+    "blobs3d": lambda: W.random_multilabel(33, (19, 21, 17), 3, E=6.0),
+    "noise3d": lambda: W.random_multilabel(34, (11, 13, 12), 3, blobs=False, E=5.0),
+    "edge_1px": lambda: W.random_multilabel(35, (1, 40), 3, blobs=False, E=6.0),
+    "edge_slice": lambda: W.random_multilabel(36, (1, 20, 23), 3, E=6.0),
+}
+
+
+@pytest.mark.parametrize("on", [True, False])
+@pytest.mark.parametrize("name", sorted(EXACT))
+def test_acceptance_with_given_gradient_is_exact(ora, name, on):
+    w = _with_topo(EXACT[name](), on)
+    print(f"[case {name} topo={int(on)} shape={w.image.shape}]", flush=True)
+    P = ora.params_of(w)
+    M = w.max_labels
+    cap = max(4096, 2 * w.labels.size)
+    ctx, img, lab = gpu_state(w, cap=cap)
+    L_o = w.labels.copy()
+    nfl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for t in range(4):
+        T = grad_table(100 + t, w.labels.size, M)
+        lin, a, b = gpu_particles(ctx)
+        lin_o, a_o, b_o = ora.particles(P, L_o)
+        assert np.array_equal(np.sort(_keys(lin, b)), _keys(lin_o, b_o))
+        g = np.zeros(cap, np.float32)
+        g[: len(lin)] = T[lin * M + b]
+        S.step_with_gradient(ctx, torch.from_numpy(g).cuda(), nfl)
+        L_next, done, moves = ora.accept_ranked(P, L_o, lin_o, a_o, b_o, T[lin_o * M + b_o],
+                                                ora.TOPO_SIMPLE if on else ora.TOPO_OFF)
+        L_g = S.get_labels(ctx).cpu().numpy()
+        assert np.array_equal(L_g, L_next), f"step {t}: {(L_g != L_next).sum()} labels differ"
+        assert int(nfl.item()) == moves
+        n_g, s_g = S.get_region_stats(ctx)
+        n_o, s1_o, _ = ora.region_stats(P, w.image, L_next)
+        assert np.array_equal(n_g, n_o)
+        assert np.allclose(s_g, s1_o, rtol=0, atol=1e-6 * max(1.0, np.abs(s1_o).max()))
+        L_o = L_next
+    lin, a, b = gpu_particles(ctx)
+    lin_o, a_o, b_o = ora.particles(P, L_o)
+    assert np.array_equal(np.sort(_keys(lin, b)), _keys(lin_o, b_o))
+
+
+def test_given_gradient_full_size_3d(ora):
+    """The 256^3 workload in the benchmark's launch configuration: one ranked,
+    controlled step with a seeded tie-rich gradient, bit-exact."""
+    w = _with_topo(W.make("ellipsoids3d_256"))
+    print("[case ellipsoids3d_256 given gradient]", flush=True)
+    P = ora.params_of(w)
+    ctx, img, lab = gpu_state(w)
+    lin, a, b = gpu_particles(ctx)
+    T = np.random.default_rng(7).integers(-64, 32, size=(w.labels.size,), dtype=np.int64)
+    T = T.astype(np.float64) / 32.0  # one label pair: index by pixel alone
+    g = np.zeros(ctx.params.max_particles, np.float32)
+    g[: len(lin)] = T[lin]
+    S.step_with_gradient(ctx, torch.from_numpy(g).cuda())
+    lin_o, a_o, b_o = ora.particles(P, w.labels)
+    L_next, done, moves = ora.accept_ranked(P, w.labels, lin_o, a_o, b_o, T[lin_o], ora.TOPO_SIMPLE)
+    L_g = S.get_labels(ctx).cpu().numpy()
+    assert np.array_equal(L_g, L_next), f"{(L_g != L_next).sum()} labels differ"
+    print(f"  N={len(lin)} moves={moves}")
+
+
+def topo_marginal(shape, lin, g, thr):
+    """Pixels whose ranked decision may depend on rounding: within two pixels
+    of a candidate with |g| <= thr or of two candidates, at most one pixel
+    apart, whose gradients differ by <= thr."""
+    nd = len(shape)
+    lin = np.asarray(lin)
+    coords = np.array(np.unravel_index(lin, shape)).T
+    seeds = set(lin[np.abs(g) <= thr].tolist())
+    cand = np.flatnonzero(g < thr)
+    by_pix = {}
+    for k in cand:
+        by_pix.setdefault(int(lin[k]), []).append(float(g[k]))
+    offs = [np.array(o) - 1 for o in np.ndindex(*(3,) * nd)]
+    for p, gs in by_pix.items():
+        c = np.array(np.unravel_index(p, shape))
+        for o in offs:
+            q = c + o
+            if np.any(q < 0) or np.any(q >= shape):
+                continue
+            qi = int(np.ravel_multi_index(tuple(q), shape))
+            for gq in by_pix.get(qi, ()):
+                for gp in gs:
+                    if (qi != p or gq != gp) and abs(gq - gp) <= thr:
+                        seeds.add(p)
+                        seeds.add(qi)
+    mark = np.zeros(shape, bool)
+    for p in seeds:
+        mark[np.unravel_index(p, shape)] = True
+    from scipy import ndimage
+    mark = ndimage.binary_dilation(mark, structure=np.ones((3,) * nd, bool), iterations=2)
+    return mark
+
+
+RUNS = {
+    "blobs2d": lambda: W.random_multilabel(41, (48, 56), 3, E=6.0, lam=0.3),
+    "blobs3d": lambda: W.random_multilabel(42, (17, 19, 18), 3, E=6.0, lam=0.4),
+    "u16_3d": lambda: W.random_multilabel(43, (14, 20, 12), 3, dtype=np.uint16, E=6.0, lam=30.0),
+    "disk2d_128": lambda: W.disk2d(),
+}
+
+
+@pytest.mark.parametrize("mode", ["sobolev", "l2"])
+@pytest.mark.parametrize("name", sorted(RUNS))
+def test_controlled_trajectory(ora, name, mode):
+    """Independent GPU and oracle trajectories with topological control agree
+    after every step until the first marginal decision."""
+    w = _with_topo(RUNS[name]())
+    m_o = ora.MODE_SOBOLEV if mode == "sobolev" else ora.MODE_L2
+    m_g = S.MODE_SOBOLEV if mode == "sobolev" else S.MODE_L2
+    print(f"[case {name} {mode} topo]", flush=True)
+    P = ora.params_of(w)
+    ctx, img, lab = gpu_state(w, cap=max(4096, 2 * w.labels.size))
+    L_o = w.labels.copy()
+    nfl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for t in range(10):
+        L_next, info = ora.step(P, w.image, L_o, m_o)
+        S.step(ctx, m_g, nfl)
+        L_g = S.get_labels(ctx).cpu().numpy()
+        diff = L_g != L_next
+        if diff.any():
+            g = info["dE_h1"] if mode == "sobolev" else info["dE_l2"]
+            thr = MARGIN * np.abs(g).max()
+            marg = topo_marginal(w.labels.shape, info["lin"], g, thr)
+            bad = np.flatnonzero(diff & ~marg)
+            assert len(bad) == 0, f"step {t}: {len(bad)} non-marginal pixels differ"
+            print(f"  step {t}: {int(diff.sum())} marginal differences; stopping comparison")
+            return
+        assert int(nfl.item()) == info["flips"]
+        L_o = L_next
+
+
+@pytest.mark.parametrize("name,iters", [("blobs2d_512", 60), ("ellipsoids3d_64_dense", 40)])
+def test_controlled_run_keeps_every_region_intact(name, iters):
+    """Without the oracle: over a run with topological control, no region of
+    label >= 1 changes its component count, its complement's component count
+    or its Euler characteristic; the same run without control does change
+    some (the inputs hold touching and close shapes)."""
+    if name == "blobs2d_512":
+        w = W.blobs2d(seed=104, side_lo=512, side_hi=512)
+    else:
+        w = W.ellipsoids3d(seed=9, n=64, count=16, axes=(6.0, 16.0), margin=6.0)
+    labs = [l for l in np.unique(w.labels) if l >= 1]
+    before = {l: topo(w.labels == l) for l in labs}
+    changed = {}
+    for on in (True, False):
+        w2 = _with_topo(w, on)
+        ctx, img, lab = gpu_state(w2)
+        S.run(ctx, iters, 0.0, S.MODE_SOBOLEV)
+        L = S.get_labels(ctx).cpu().numpy()
+        changed[on] = [l for l in labs if topo(L == l) != before[l]]
+        print(f"  topo={int(on)}: regions changed {changed[on]}", flush=True)
+    assert changed[True] == []
+    assert changed[False] != []
+
+
+def test_auto_mode_with_control_matches_oracle(ora):
+    w = _with_topo(W.disk2d())
+    print("[case disk2d_128 auto topo]", flush=True)
+    P = ora.params_of(w)
+    o = ora.run_ex(P, w.image, w.labels, ora.MODE_AUTO, 200, 1e-3)
+    ctx, img, lab = gpu_state(w, cap=2 * w.labels.size)
+    t_g = S.run(ctx, 200, 1e-3, S.MODE_AUTO)
+    L_g = S.get_labels(ctx).cpu().numpy()
+    gn, gf, gb = S.get_history(ctx, reversals=True)
+    if (L_g != o["L"]).any() or t_g != o["t"]:
+        pytest.skip("trajectories split at a marginal decision")
+    assert np.array_equal(gn, o["n"]) and np.array_equal(gf, o["flips"])
+    assert np.array_equal(gb, o["reversals"])
+    assert S.gradient_switch(ctx) == o["switch"]
+
+
+def test_capacity_roll_back_with_control():
+    """A controlled step that overflows the capacity is rolled back exactly."""
+    w = _with_topo(W.disk2d())
+    ctx, img, lab = S.from_workload(w, max_particles=330)
+    S.init_labels(ctx, img, lab)
+    lin0, a0, b0 = gpu_particles(ctx)
+    n0, s0 = S.get_region_stats(ctx)
+    S.step(ctx)
+    with pytest.raises(S.SobrcError) as e:
+        S.ctx_sync(ctx)
+    assert e.value.code == S.ECAPACITY
+    assert (S.get_labels(ctx).cpu().numpy() == w.labels).all()
+    n1, s1 = S.get_region_stats(ctx)
+    assert np.array_equal(n0, n1) and np.array_equal(s0, s1)
+
+
+def test_controlled_contexts_are_not_batched():
+    w = _with_topo(W.disk2d())
+    ctx, img, lab = gpu_state(w)
+    batch = S.Batch(2)
+    try:
+        with pytest.raises(S.SobrcError) as e:
+            batch.set(0, ctx)
+        assert e.value.code == S.EINVAL
+    finally:
+        batch.close()
