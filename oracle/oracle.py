@@ -28,7 +28,7 @@ class Params(C.Structure):
         ("model", C.c_int32), ("ps_radius", C.c_int32),
         ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
         ("max_labels", C.c_int32), ("threads", C.c_int32), ("noise", C.c_int32),
-        ("topo", C.c_int32),
+        ("topo", C.c_int32), ("psf_sigma", C.c_double),
     ]
 
 
@@ -78,6 +78,14 @@ def lib():
         L.ora_accept_ranked.restype = C.c_int64
         L.ora_accept_ranked.argtypes = [P(Params), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+        L.ora_psf_radius.restype = C.c_int32
+        L.ora_psf_radius.argtypes = [C.c_double]
+        L.ora_psf_taps.restype = None
+        L.ora_psf_taps.argtypes = [C.c_double, C.c_void_p]
+        L.ora_deconv_theta.restype = None
+        L.ora_deconv_theta.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_deconv_model.restype = None
+        L.ora_deconv_model.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_void_p]
         L.ora_energy_pc.restype = C.c_double
         L.ora_energy_pc.argtypes = [P(Params), C.c_void_p, C.c_void_p]
         L.ora_conv_closed_curve.restype = None
@@ -92,20 +100,20 @@ def _ptr(a):
 
 
 def make_params(shape, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0, max_labels=2,
-                threads=1, noise=GAUSS, topo=TOPO_OFF) -> Params:
+                threads=1, noise=GAUSS, topo=TOPO_OFF, psf_sigma=0.0) -> Params:
     if len(shape) == 2:
         ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
     else:
         ndim, (nz, ny, nx) = 3, shape
     return Params(ndim, nx, ny, nz, model, ps_radius, float(E), float(eps), float(lam),
-                  max_labels, threads, noise, topo)
+                  max_labels, threads, noise, topo, float(psf_sigma))
 
 
 def params_of(w, threads=1) -> Params:
     """Parameters of a workloads.Workload."""
     return make_params(w.image.shape, w.E, w.lam, w.model, w.ps_radius, w.eps,
                        w.max_labels, threads, getattr(w, "noise", GAUSS),
-                       getattr(w, "topo", TOPO_OFF))
+                       getattr(w, "topo", TOPO_OFF), getattr(w, "psf_sigma", 0.0))
 
 
 def _img(I):
@@ -225,6 +233,26 @@ def accept_ranked(P: Params, L, lin, a, b, g, topo=TOPO_SIMPLE):
     m = lib().ora_accept_ranked(C.byref(P), _ptr(L), len(lin), _ptr(lin), _ptr(a), _ptr(b),
                                 _ptr(g), int(topo), _ptr(done))
     return L, done.astype(bool), m
+
+
+def psf_taps(sigma):
+    r = lib().ora_psf_radius(float(sigma))
+    k = np.zeros(2 * r + 1)
+    lib().ora_psf_taps(float(sigma), _ptr(k))
+    return k
+
+
+def deconv_theta(P: Params, I, L):
+    th = np.zeros(P.max_labels)
+    lib().ora_deconv_theta(C.byref(P), _ptr(_img(I)), _ptr(_lab(L)), _ptr(th))
+    return th
+
+
+def deconv_model(P: Params, L, theta):
+    L = _lab(L)
+    J = np.zeros(L.shape)
+    lib().ora_deconv_model(C.byref(P), _ptr(L), _ptr(np.ascontiguousarray(theta, np.float64)), _ptr(J))
+    return J
 
 
 def reversals(L_prev, L_next, stamp, t):

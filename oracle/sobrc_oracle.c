@@ -25,6 +25,9 @@
  *  - Poisson noise (ORA_POISSON): pixel energy J - I log J; a move changes it
  *    with both expected intensities held at their current values (region
  *    means for PC, local means for PS), means below 1e-6 raised to 1e-6;
+ *  - deconvolving model (psf_sigma > 0): separable Gaussian PSF truncated at
+ *    3 sigma, zero outside the image; theta by least squares over the image
+ *    for the labels at the start of the iteration, held fixed for every move;
  *  - length prior: number of face-adjacent pixel pairs with different labels;
  *  - acceptance: every particle with gradient < 0 is a candidate, per pixel the
  *    smallest gradient wins (ties: smaller target label), all chosen moves are
@@ -182,10 +185,203 @@ static double poisson_move(double v, double m_a, double m_b)
     return (jb - v * log(jb)) - (ja - v * log(ja));
 }
 
+/* --- deconvolving model (Eq. (8)) ---------------------------------------- */
+
+int32_t ora_psf_radius(double sigma)
+{
+    return (int32_t)ceil(3.0 * sigma);
+}
+
+void ora_psf_taps(double sigma, double* taps)
+{
+    int r = ora_psf_radius(sigma);
+    double sum = 0.0;
+    for (int t = -r; t <= r; ++t) {
+        taps[t + r] = exp(-(double)(t * t) / (2.0 * sigma * sigma));
+        sum += taps[t + r];
+    }
+    for (int t = -r; t <= r; ++t)
+        taps[t + r] /= sum;
+}
+
+/* out(y) = sum over image pixels x with |y - x| <= r per axis of
+ * K(y - x) f(x), written out directly (no separable passes). */
+static void psf_apply(const ora_params* P, const double* f, double* out)
+{
+    int r = ora_psf_radius(P->psf_sigma);
+    double* k = (double*)malloc(sizeof(double) * (size_t)(2 * r + 1));
+    ora_psf_taps(P->psf_sigma, k);
+    int rz = P->ndim == 3 ? r : 0;
+    int64_t nvox = (int64_t)P->nx * P->ny * P->nz;
+#pragma omp parallel for schedule(static) num_threads(nthreads(P)) if (nthreads(P) > 1)
+    for (int64_t i = 0; i < nvox; ++i) {
+        int x, y, z;
+        coords_of(P, i, &x, &y, &z);
+        double acc = 0.0;
+        for (int dz = -rz; dz <= rz; ++dz)
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    if (!in_bounds(P, x + dx, y + dy, z + dz))
+                        continue;
+                    double kk = k[dx + r] * k[dy + r] * (P->ndim == 3 ? k[dz + r] : 1.0);
+                    acc += kk * f[lin_of(P, x + dx, y + dy, z + dz)];
+                }
+        out[i] = acc;
+    }
+    free(k);
+}
+
+/* Solve the n x n system A t = c in place (Gaussian elimination with partial
+ * pivoting).  Returns 0 if a pivot vanishes. */
+static int solve_dense(int n, double* A, double* c, double* t)
+{
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(A[r * n + col]) > fabs(A[piv * n + col]))
+                piv = r;
+        if (A[piv * n + col] == 0.0)
+            return 0;
+        if (piv != col) {
+            for (int j = 0; j < n; ++j) {
+                double tmp = A[col * n + j];
+                A[col * n + j] = A[piv * n + j];
+                A[piv * n + j] = tmp;
+            }
+            double tmp = c[col];
+            c[col] = c[piv];
+            c[piv] = tmp;
+        }
+        for (int r = col + 1; r < n; ++r) {
+            double f = A[r * n + col] / A[col * n + col];
+            for (int j = col; j < n; ++j)
+                A[r * n + j] -= f * A[col * n + j];
+            c[r] -= f * c[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double acc = c[r];
+        for (int j = r + 1; j < n; ++j)
+            acc -= A[r * n + j] * t[j];
+        t[r] = acc / A[r * n + r];
+    }
+    return 1;
+}
+
+void ora_deconv_theta(const ora_params* P, const double* I, const int32_t* L, double* theta)
+{
+    int M = P->max_labels;
+    int64_t nvox = (int64_t)P->nx * P->ny * P->nz;
+    /* u_l = K * chi_l for the labels present */
+    int* idx = (int*)malloc(sizeof(int) * (size_t)M);
+    int n = 0;
+    for (int l = 0; l < M; ++l) {
+        idx[l] = -1;
+        theta[l] = 0.0;
+        for (int64_t i = 0; i < nvox; ++i)
+            if (L[i] == l) {
+                idx[l] = n++;
+                break;
+            }
+    }
+    double* u = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)nvox);
+    double* chi = (double*)malloc(sizeof(double) * (size_t)nvox);
+    for (int l = 0; l < M; ++l) {
+        if (idx[l] < 0)
+            continue;
+        for (int64_t i = 0; i < nvox; ++i)
+            chi[i] = L[i] == l ? 1.0 : 0.0;
+        psf_apply(P, chi, u + (size_t)idx[l] * (size_t)nvox);
+    }
+    /* normal equations of min sum (I - sum_l theta_l u_l)^2 */
+    double* A = (double*)calloc((size_t)(n * n > 0 ? n * n : 1), sizeof(double));
+    double* c = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double* t = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    for (int p = 0; p < n; ++p) {
+        const double* up = u + (size_t)p * (size_t)nvox;
+        for (int q = 0; q < n; ++q) {
+            const double* uq = u + (size_t)q * (size_t)nvox;
+            double acc = 0.0;
+            for (int64_t i = 0; i < nvox; ++i)
+                acc += up[i] * uq[i];
+            A[p * n + q] = acc;
+        }
+        double acc = 0.0;
+        for (int64_t i = 0; i < nvox; ++i)
+            acc += up[i] * I[i];
+        c[p] = acc;
+    }
+    if (n > 0 && solve_dense(n, A, c, t))
+        for (int l = 0; l < M; ++l)
+            if (idx[l] >= 0)
+                theta[l] = t[idx[l]];
+    free(idx);
+    free(u);
+    free(chi);
+    free(A);
+    free(c);
+    free(t);
+}
+
+void ora_deconv_model(const ora_params* P, const int32_t* L, const double* theta, double* J)
+{
+    int64_t nvox = (int64_t)P->nx * P->ny * P->nz;
+    double* s = (double*)malloc(sizeof(double) * (size_t)nvox);
+    for (int64_t i = 0; i < nvox; ++i)
+        s[i] = theta[L[i]];
+    psf_apply(P, s, J);
+    free(s);
+}
+
+/* Data term of moving pixel i by delta under the deconvolving model: the
+ * change of sum_y (R(y) - delta K(y - x))^2 over the image, R = I - J. */
+static double deconv_move(const ora_params* P, const double* R, const double* k, int r, int64_t i, double delta)
+{
+    int x, y, z;
+    coords_of(P, i, &x, &y, &z);
+    int rz = P->ndim == 3 ? r : 0;
+    double d = 0.0;
+    for (int dz = -rz; dz <= rz; ++dz)
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
+                if (!in_bounds(P, x + dx, y + dy, z + dz))
+                    continue;
+                double kk = k[dx + r] * k[dy + r] * (P->ndim == 3 ? k[dz + r] : 1.0);
+                double rv = R[lin_of(P, x + dx, y + dy, z + dz)];
+                d += (rv - delta * kk) * (rv - delta * kk) - rv * rv;
+            }
+    return d;
+}
+
 void ora_l2diff(const ora_params* P, const double* I, const int32_t* L,
                 int64_t np, const int64_t* lin, const int32_t* a, const int32_t* b,
                 double* dE)
 {
+    if (P->psf_sigma > 0.0) {
+        int M = P->max_labels;
+        int64_t nvox = (int64_t)P->nx * P->ny * P->nz;
+        int r = ora_psf_radius(P->psf_sigma);
+        double* theta = (double*)malloc(sizeof(double) * (size_t)M);
+        double* R = (double*)malloc(sizeof(double) * (size_t)nvox);
+        double* k = (double*)malloc(sizeof(double) * (size_t)(2 * r + 1));
+        ora_psf_taps(P->psf_sigma, k);
+        ora_deconv_theta(P, I, L, theta);
+        ora_deconv_model(P, L, theta, R);
+        for (int64_t i = 0; i < nvox; ++i)
+            R[i] = I[i] - R[i];
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads(P)) if (nthreads(P) > 1)
+        for (int64_t q = 0; q < np; ++q) {
+            int x, y, z;
+            coords_of(P, lin[q], &x, &y, &z);
+            double d_ext = deconv_move(P, R, k, r, lin[q], theta[b[q]] - theta[a[q]]);
+            double d_int = (double)(face_count(P, L, x, y, z, a[q]) - face_count(P, L, x, y, z, b[q]));
+            dE[q] = d_ext + P->lambda * d_int;
+        }
+        free(theta);
+        free(R);
+        free(k);
+        return;
+    }
     int M = P->max_labels;
     int64_t* n = (int64_t*)calloc((size_t)M, sizeof(int64_t));
     double* s1 = (double*)calloc((size_t)M, sizeof(double));

@@ -34,7 +34,22 @@ typedef struct {
     int32_t threads;           /* OpenMP threads for per-particle loops (<=1: serial) */
     int32_t noise;             /* ORA_GAUSS or ORA_POISSON pixel noise */
     int32_t topo;              /* ORA_TOPO_OFF or ORA_TOPO_SIMPLE acceptance */
+    double psf_sigma;          /* > 0: deconvolving model with a Gaussian PSF (PC, Gaussian noise) */
 } ora_params;
+
+/* Deconvolving image model (Methods, Eq. (8): J = s_theta(Gamma) * K).  K is
+ * a separable Gaussian point-spread function: per axis the taps
+ * exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma), normalised to sum 1, and
+ * K(d) their product over the axes; s is zero outside the image.  The region
+ * intensities theta (photometric estimate) minimise sum_y (I(y) - J(y))^2
+ * over the image for the current labels (least squares; a label with no
+ * pixel gets theta 0).  A move of pixel x from a to b changes s(x) by
+ * delta = theta_b - theta_a with theta held fixed, so its data term is
+ * sum_y [(I(y) - J(y) - delta K(y - x))^2 - (I(y) - J(y))^2] over the image. */
+int32_t ora_psf_radius(double sigma);
+void ora_psf_taps(double sigma, double* taps); /* 2 ora_psf_radius(sigma) + 1 taps */
+void ora_deconv_theta(const ora_params* P, const double* I, const int32_t* L, double* theta);
+void ora_deconv_model(const ora_params* P, const int32_t* L, const double* theta, double* J);
 
 /* Acceptance of the moves.  OFF: simultaneous, per pixel the smallest
  * gradient.  SIMPLE: the moves are ranked by gradient (most negative first)
@@ -67,8 +82,9 @@ void ora_region_stats(const ora_params* P, const double* I, const int32_t* L,
                       int64_t* n, double* s1, double* s2);
 
 /* L2-type gradient: per-particle energy difference of the single move
- * a -> b (Eqs. (10)-(11)), piecewise-constant or piecewise-smooth model plus
- * lambda times the change in contour length. */
+ * a -> b (Eqs. (10)-(11)), piecewise-constant or piecewise-smooth model (or
+ * the deconvolving model when P->psf_sigma > 0) plus lambda times the change
+ * in contour length. */
 void ora_l2diff(const ora_params* P, const double* I, const int32_t* L,
                 int64_t np, const int64_t* lin, const int32_t* a, const int32_t* b,
                 double* dE);

@@ -55,6 +55,7 @@ class Workload:
     max_labels: int = 2
     noise: int = GAUSS
     topo: int = 0              # 1: ranked acceptance with topological control
+    psf_sigma: float = 0.0     # > 0: deconvolving model, Gaussian PSF of this width (pixels)
 
     @property
     def ndim(self) -> int:
@@ -269,6 +270,33 @@ def blobs2d(seed: int = 100, side_lo: int = 128, side_hi: int = 1024, E: float =
                     iterations=iterations)
 
 
+def deconv2d(seed: int = 11, n: int = 512, psf_sigma: float = 15.0, count: int = 6,
+             noise: float = 0.05, E: float = 8.0, lam: float = 1e-3, iterations: int = 100) -> Workload:
+    """Blurred 2D scene for the deconvolving model (after the paper's
+    deconvolution example): n x n fp32, `count` disks or ellipses (semi-axes
+    25-70 px, painter's order) of intensity 1.0 on background 0.2, blurred by
+    a Gaussian PSF of width psf_sigma (zero outside the image, truncated at
+    3 sigma), Gaussian noise of the given sigma.  Initial labels: the shapes
+    shrunk by 6 px.  Piecewise-constant deconvolving model, E = 8."""
+    from scipy import ndimage
+    rng = np.random.Generator(np.random.PCG64(seed))
+    truth = np.zeros((n, n), bool)
+    lab = np.zeros((n, n), dtype=np.int32)
+    for _ in range(count):
+        a = rng.uniform(25.0, 70.0)
+        b = a if rng.random() < 0.5 else rng.uniform(25.0, 70.0)
+        phi = rng.uniform(0.0, np.pi)
+        cx, cy = rng.uniform(80.0, n - 80.0), rng.uniform(80.0, n - 80.0)
+        xs, ys = _grid2d(n, n)
+        truth |= _inside_ellipse(xs, ys, cx, cy, a, b, phi)
+        lab[_inside_ellipse(xs, ys, cx, cy, a, b, phi, shrink=6.0)] = 1
+    scene = 0.2 + 0.8 * truth.astype(np.float64)
+    blurred = ndimage.gaussian_filter(scene, psf_sigma, mode="constant", cval=0.0, truncate=3.0)
+    img = (blurred + rng.normal(0.0, noise, size=(n, n))).astype(np.float32)
+    return Workload(f"deconv2d_{n}", img, lab, E=E, lam=lam, model=PC, iterations=iterations,
+                    psf_sigma=psf_sigma)
+
+
 def batch2d(n_images: int = 64, seed0: int = 100) -> list:
     """The batched workload: n_images independent blobs2d images, seeds
     seed0 .. seed0 + n_images - 1."""
@@ -303,6 +331,7 @@ CONFIGS = {
     "disk2d_128": disk2d,
     "ellipses2d_1024": ellipses2d,
     "ellipsoids3d_256": ellipsoids3d,
+    "deconv2d_512": deconv2d,
 }
 
 
