@@ -347,6 +347,7 @@ def main():
                    "image_dtype": str(w.image.dtype), "image_model": "piecewise-constant"
                    if w.model == W.PC else "piecewise-smooth", "E": w.E, "lambda": w.lam,
                    "acceptance": "ranked, topology-controlled" if a.topo else "simultaneous",
+                   "psf_sigma": w.psf_sigma,
                    "particles_init": n0, "particles_mean": updates / a.steps,
                    "flips_last": int(hf[-1]) if len(hf) else 0},
     }

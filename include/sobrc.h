@@ -82,6 +82,17 @@ enum { SOBRC_MODE_SOBOLEV = 0, SOBRC_MODE_L2 = 1, SOBRC_MODE_AUTO = 2 };
  * Contexts with SIMPLE take 8 bytes per pixel and 1 per particle more
  * workspace and are not batched. */
 enum { SOBRC_TOPO_OFF = 0, SOBRC_TOPO_SIMPLE = 1 };
+/* Deconvolving image model (Methods, Eq. (8): J = s_theta(Gamma) * K), used
+ * when params.psf_sigma > 0.  K is a separable Gaussian point-spread function:
+ * per axis the taps exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma),
+ * normalised to sum 1; s is zero outside the image.  At the start of every
+ * gradient evaluation the region intensities theta are the least-squares fit
+ * of sum_l theta_l (K * chi_l) to the image (labels without pixels get 0);
+ * a move of pixel x from a to b then has the data term
+ * sum_y [(I - J - delta K(y - x))^2 - (I - J)^2] over the image, delta =
+ * theta_b - theta_a, theta held fixed.  Needs SOBRC_PC, SOBRC_NOISE_GAUSS and
+ * max_labels <= 4; takes (max_labels + 4) x 4 bytes per pixel more workspace;
+ * not batched. */
 
 typedef struct {
     int32_t ndim;          /* 2 or 3 */
@@ -96,6 +107,7 @@ typedef struct {
     int64_t max_particles; /* particle capacity, 1 <= max_particles < 2^31 */
     int32_t noise;         /* SOBRC_NOISE_GAUSS or SOBRC_NOISE_POISSON */
     int32_t topo;          /* SOBRC_TOPO_OFF or SOBRC_TOPO_SIMPLE (acceptance, see below) */
+    double psf_sigma;      /* 0, or the width (pixels, <= 16) of a Gaussian PSF: deconvolving model */
 } sobrc_params;
 
 typedef struct sobrc_ctx sobrc_ctx;
@@ -292,7 +304,7 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n,
  * SOBRC_K_* below), the summed milliseconds and launch count since the last
  * reset.  Kinds: */
 enum { SOBRC_K_L2DIFF = 0, SOBRC_K_SOBOLEV = 1, SOBRC_K_FLIP = 2, SOBRC_K_COUNT = 3,
-       SOBRC_K_SCAN = 4, SOBRC_K_WRITE = 5, SOBRC_K_TOPO = 6, SOBRC_K_NKINDS = 7 };
+       SOBRC_K_SCAN = 4, SOBRC_K_WRITE = 5, SOBRC_K_TOPO = 6, SOBRC_K_DECONV = 7, SOBRC_K_NKINDS = 8 };
 int32_t profile_enable(sobrc_ctx* ctx, int32_t on);
 int32_t profile_read(sobrc_ctx* ctx, double* h_ms, int64_t* h_launches, int32_t reset);
 

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsobrc.so")
-SOURCES = ["sobrc_kernels.hip", "sobrc_abi.hip"]
+SOURCES = ["sobrc_kernels.hip", "sobrc_deconv.hip", "sobrc_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -73,6 +73,11 @@ int32_t validate(const sobrc_params* p)
         return fail(SOBRC_EINVAL, "max_particles must lie in [1, 2^31-1]");
     if (p->topo != SOBRC_TOPO_OFF && p->topo != SOBRC_TOPO_SIMPLE)
         return fail(SOBRC_EINVAL, "topo must be SOBRC_TOPO_OFF or SOBRC_TOPO_SIMPLE");
+    if (!(p->psf_sigma >= 0.0 && p->psf_sigma <= kPsfMaxR / 3.0))
+        return fail(SOBRC_EINVAL, "psf_sigma must lie in [0, %d] (got %g)", kPsfMaxR / 3, p->psf_sigma);
+    if (p->psf_sigma > 0.0 && (p->model != SOBRC_PC || p->noise != SOBRC_NOISE_GAUSS || p->max_labels > kDeconvM))
+        return fail(SOBRC_EINVAL, "the deconvolving model needs SOBRC_PC, SOBRC_NOISE_GAUSS and max_labels <= %d",
+                    kDeconvM);
     return SOBRC_OK;
 }
 
@@ -125,6 +130,7 @@ Geom make_geom(const sobrc_params* p)
     g.model = p->model;
     g.noise = p->noise;
     g.topo = p->topo;
+    g.psf = p->psf_sigma > 0.0 ? 1 : 0;
     g.img_u16 = p->image_dtype == SOBRC_U16;
     g.lambda = (float)p->lambda;
     g.fx_scale = 1.0;
@@ -176,7 +182,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t lab, fstamp, dcnt, dlist, dflat, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
-        part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, tstate, tmark, tlist0, tlist1, pmap, ds;
+        part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, tstate, tmark, tlist0, tlist1, pmap, du, dt0, dt1, dC, dN, dw, dtheta, dpart, ds;
     size_t total;
 };
 
@@ -224,6 +230,15 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     L.tlist0 = take(topo ? (size_t)g.ntiles * 4 : 0);
     L.tlist1 = take(topo ? (size_t)g.ntiles * 4 : 0);
     L.pmap = take(topo ? (size_t)nvox * 8 : 0);
+    const bool psf = p->psf_sigma > 0.0;  // images of the deconvolving model
+    L.du = take(psf ? (size_t)(p->max_labels - 1) * nvox * 4 : 0);
+    L.dt0 = take(psf ? (size_t)nvox * 4 : 0);
+    L.dt1 = take(psf ? (size_t)nvox * 4 : 0);
+    L.dC = take(psf ? (size_t)nvox * 4 : 0);
+    L.dN = take(psf ? (size_t)nvox * 4 : 0);
+    L.dw = take(psf ? (size_t)nvox * 4 : 0);
+    L.dtheta = take(psf ? (size_t)p->max_labels * 8 : 0);
+    L.dpart = take(psf ? (size_t)kDeconvGrid * kDeconvSums * 8 : 0);
     L.ds = take(sizeof(DevState));
     L.total = o;
     return L;
@@ -265,6 +280,14 @@ Bufs carve(const Layout& L, char* base, long long cap)
     b.tlist[0] = (unsigned*)(base + L.tlist0);
     b.tlist[1] = (unsigned*)(base + L.tlist1);
     b.pmap = (unsigned long long*)(base + L.pmap);
+    b.du = (float*)(base + L.du);
+    b.dt[0] = (float*)(base + L.dt0);
+    b.dt[1] = (float*)(base + L.dt1);
+    b.dC = (float*)(base + L.dC);
+    b.dN = (float*)(base + L.dN);
+    b.dw = (float*)(base + L.dw);
+    b.dtheta = (double*)(base + L.dtheta);
+    b.dpart = (double*)(base + L.dpart);
     b.ds = (DevState*)(base + L.ds);
     b.cap = (unsigned)cap;
     return b;
@@ -299,10 +322,31 @@ int32_t upload_tables(const Geom& g, double E, double eps, float* d_W, SobW* sw,
 
 }  // namespace
 
+// Per-axis taps of the Gaussian point-spread function (deconvolving model):
+// exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma), normalised to sum 1.
+Psf make_psf(double sigma)
+{
+    Psf k{};
+    if (!(sigma > 0.0))
+        return k;
+    k.r = (int)ceil(3.0 * sigma);
+    double t[kPsfTaps], sum = 0.0;
+    for (int i = -k.r; i <= k.r; ++i) {
+        t[i + k.r] = exp(-(double)(i * i) / (2.0 * sigma * sigma));
+        sum += t[i + k.r];
+    }
+    for (int i = 0; i <= 2 * k.r; ++i) {
+        k.k[i] = (float)(t[i] / sum);
+        k.k2[i] = (float)((t[i] / sum) * (t[i] / sum));
+    }
+    return k;
+}
+
 struct sobrc_ctx {
     sobrc_params p;
     Geom g;
     SobW sw{};
+    Psf psf{};
     Layout L;
     Bufs b;
     const void* image = nullptr;
@@ -400,6 +444,9 @@ int32_t launch_step(sobrc_ctx* c, int mode, int32_t* d_nflips, float tol, hipStr
     // auto mode: the Sobolev kernel skips itself and the acceptance reads the
     // L2 gradients once the device has switched (latched per step)
     const int flags = kGate | (mode == SOBRC_MODE_AUTO ? kAuto : 0);
+    if (g.psf)
+        SOBRC_TRY(timed(c, SOBRC_K_DECONV, s, "k_deconv",
+                        [&] { return launch_deconv(g, b, c->psf, c->image, s); }));
     SOBRC_TRY(timed(c, SOBRC_K_L2DIFF, s, "k_l2diff",
                     [&] { return launch_l2diff(g, b, c->image, cur, b.dE, 1, s); }));
     const float* grad = b.dE;
@@ -514,6 +561,7 @@ int32_t ctx_create(const sobrc_params* params, void* d_workspace, size_t bytes, 
     c->g = g;
     c->L = L;
     c->b = carve(L, (char*)d_workspace, params->max_particles);
+    c->psf = make_psf(params->psf_sigma);
     *out = c;
     return SOBRC_OK;
 }
@@ -583,6 +631,8 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
         g.fx_inv = ldexp(1.0, -s2);
     }
     SOBRC_HIP(launch_stats_init(g, b, d_image, s), "k_stats_init");
+    if (g.psf)
+        SOBRC_HIP(launch_deconv_init(g, b, c->psf, s), "k_psf_pass");
     SOBRC_HIP(launch_count(g, b, 0, 0, 1, s), "k_count");
     SOBRC_HIP(launch_scan(g, b, 0, 0, 1, 0.f, nullptr, 0, s), "k_scan");
     SOBRC_HIP(launch_write(g, b, d_image, 0, 0, nullptr, nullptr, 0, 1, s), "k_write");
@@ -604,6 +654,9 @@ int32_t compute_l2_diff(sobrc_ctx* c, float* d_dE_l2, void* stream)
     if (!d_dE_l2)
         return fail(SOBRC_EINVAL, "output is NULL");
     hipStream_t s = (hipStream_t)stream;
+    if (c->g.psf)
+        SOBRC_TRY(timed(c, SOBRC_K_DECONV, s, "k_deconv",
+                        [&] { return launch_deconv(c->g, c->b, c->psf, c->image, s); }));
     return timed(c, SOBRC_K_L2DIFF, s, "k_l2diff",
                  [&] { return launch_l2diff(c->g, c->b, c->image, c->cur, d_dE_l2, 0, s); });
 }
@@ -1044,8 +1097,8 @@ int32_t batch_set(sobrc_batch* B, int32_t slot, sobrc_ctx* c, void* stream)
     if (c) {
         if (!c->initialized)
             return fail(SOBRC_ESTATE, "context not initialised");
-        if (c->g.topo)
-            return fail(SOBRC_EINVAL, "contexts with topological control are not batched");
+        if (c->g.topo || c->g.psf)
+            return fail(SOBRC_EINVAL, "contexts with topological control or a PSF are not batched");
         if (c->batch && (c->batch != B || B->slot[slot] != c))
             return fail(SOBRC_ESTATE, "context is already in a batch slot");
         bool any = false;

@@ -55,6 +55,18 @@ struct SobW {
     int rw[kMaxLim];
 };
 
+// Deconvolving model: separable Gaussian PSF taps (per axis), passed by value.
+constexpr int kPsfMaxR = 48;                 // sigma <= 16, truncated at 3 sigma
+constexpr int kPsfTaps = 2 * kPsfMaxR + 1;
+constexpr int kDeconvM = 4;                  // labels of a deconvolving context
+constexpr int kDeconvSums = kDeconvM * (kDeconvM + 1) / 2 + kDeconvM;  // normal-equation sums
+constexpr int kDeconvGrid = 512;             // blocks of the per-pixel deconvolution kernels
+struct Psf {
+    int r;                 // radius: taps t = -r .. r
+    float k[kPsfTaps];     // K per axis, sum 1
+    float k2[kPsfTaps];    // K^2 per axis (for the move's own term)
+};
+
 // error bits kept on the device (sticky until init_labels)
 constexpr unsigned kErrCapacity = 1u;
 constexpr unsigned kErrLabel = 2u;
@@ -92,6 +104,7 @@ struct Geom {
     int sob_grid;               // blocks of the Sobolev kernels (multiple of 8)
     int dlistm;                 // dirty tiles go through a flat list balanced over all waves (ge <= kMaxGrid)
     int topo;                   // ranked acceptance with topological control
+    int psf;                    // deconvolving model (Gaussian PSF)
 };
 
 // Device-resident control block of a context.
@@ -159,6 +172,14 @@ struct Bufs {
     unsigned* tmark;         // per tile: odd stamp of the iteration that listed it
     unsigned* tlist[2];      // tiles of the even / odd rounds
     unsigned long long* pmap;  // per pixel: smallest undecided key << 16 | label (~0: no candidate)
+    // deconvolving model (psf only)
+    float* du;               // K * chi_l for labels 1 .. M-1, nvox each
+    float* dt[2];            // scratch images of the separable passes
+    float* dC;               // K * (I - J): correlation of the residual with the PSF
+    float* dN;               // sum over the image of K(y - x)^2, per pixel x
+    float* dw;               // K * 1: PSF mass inside the image, per pixel
+    double* dtheta;          // region intensities (least squares), M
+    double* dpart;           // per block: normal-equation partial sums (kDeconvSums)
     DevState* ds;
     unsigned cap;
 };
@@ -202,6 +223,8 @@ hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, c
 hipError_t launch_topo(const Geom& g, const Bufs& b, int cur, const float* grad, const float* grad_l2,
                        int flags, hipStream_t s);
 hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, hipStream_t s);
+hipError_t launch_deconv_init(const Geom& g, const Bufs& b, const Psf& k, hipStream_t s);
+hipError_t launch_deconv(const Geom& g, const Bufs& b, const Psf& k, const void* img, hipStream_t s);
 hipError_t launch_scan(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol,
                        int32_t* d_nflips, int gated, hipStream_t s);
 hipError_t launch_write(const Geom& g, const Bufs& b, const void* img, int cur, int nxt,

@@ -1159,7 +1159,11 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
         SOBRC_FACE(z + 1 < g.nz, i + nxy)
 #undef SOBRC_FACE
         float dext;
-        if (g.model == 0) {
+        if (g.psf) {
+            // deconvolving model: delta^2 N(x) - 2 delta C(x), theta held fixed
+            const float d = (float)(b.dtheta[bl] - b.dtheta[a]);
+            dext = d * d * b.dN[i] - 2.f * d * b.dC[i];
+        } else if (g.model == 0) {
             float4 sa = b.lstat[a], sb = b.lstat[bl];
             if (g.noise) {
                 dext = poisson_move(v, sa.x, sb.x);

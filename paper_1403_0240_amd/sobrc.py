@@ -20,8 +20,9 @@ PC, PS = 0, 1
 NOISE_GAUSS, NOISE_POISSON = 0, 1
 MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 TOPO_OFF, TOPO_SIMPLE = 0, 1
-K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE, K_TOPO = range(7)
-KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write", "k_topo")
+K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE, K_TOPO, K_DECONV = range(8)
+KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write", "k_topo",
+                "k_deconv")
 
 EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "compute_l2_diff",
            "sobolev_smooth", "step", "step_with_gradient", "run", "ctx_sync", "get_particles", "get_labels",
@@ -43,7 +44,7 @@ class Params(C.Structure):
         ("image_dtype", C.c_int32), ("model", C.c_int32), ("ps_radius", C.c_int32),
         ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
         ("max_labels", C.c_int32), ("max_particles", C.c_int64), ("noise", C.c_int32),
-        ("topo", C.c_int32),
+        ("topo", C.c_int32), ("psf_sigma", C.c_double),
     ]
 
 
@@ -116,7 +117,7 @@ def _ptr(t):
 
 
 def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0,
-                max_labels=2, max_particles=1 << 20, noise=0, topo=TOPO_OFF) -> Params:
+                max_labels=2, max_particles=1 << 20, noise=0, topo=TOPO_OFF, psf_sigma=0.0) -> Params:
     """Parameters for an image of numpy-style shape (ny, nx) or (nz, ny, nx)."""
     if len(shape) == 2:
         ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
@@ -124,7 +125,7 @@ def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.
         ndim, (nz, ny, nx) = 3, shape
     dt = U16 if image_dtype in (torch.uint16, "uint16", U16) else F32
     return Params(ndim, nx, ny, nz, dt, model, ps_radius, float(E), float(eps), float(lam),
-                  max_labels, int(max_particles), int(noise), int(topo))
+                  max_labels, int(max_particles), int(noise), int(topo), float(psf_sigma))
 
 
 def workspace_size(params: Params) -> int:
@@ -329,7 +330,8 @@ def from_workload(w, max_particles=None, device="cuda"):
         max_particles = default_capacity(w.image.shape)
     dt = U16 if w.image.dtype == np.uint16 else F32
     p = make_params(w.image.shape, dt, w.E, w.lam, w.model, w.ps_radius, w.eps,
-                    w.max_labels, max_particles, getattr(w, "noise", 0), getattr(w, "topo", 0))
+                    w.max_labels, max_particles, getattr(w, "noise", 0), getattr(w, "topo", 0),
+                    getattr(w, "psf_sigma", 0.0))
     ctx = Context(p, device)
     if dt == U16:
         img = torch.from_numpy(np.ascontiguousarray(w.image, np.uint16)).to(device)

@@ -45,7 +45,11 @@ def _p(**kw):
                                 dict(image_dtype=7), dict(model=3), dict(model=S.PS, ps_radius=1),
                                 dict(E=0.0), dict(E=65.0), dict(eps=0.0), dict(lam=-1.0),
                                 dict(max_labels=1), dict(max_labels=65536), dict(max_particles=0),
-                                dict(noise=2), dict(noise=-1), dict(topo=2), dict(topo=-1)])
+                                dict(noise=2), dict(noise=-1), dict(topo=2), dict(topo=-1),
+                                dict(psf_sigma=-1.0), dict(psf_sigma=16.5),
+                                dict(psf_sigma=2.0, model=S.PS, ps_radius=3),
+                                dict(psf_sigma=2.0, noise=S.NOISE_POISSON),
+                                dict(psf_sigma=2.0, max_labels=5)])
 def test_bad_params(L, kw):
     n = C.c_size_t(0)
     assert L.workspace_size(C.byref(_p(**kw)), C.byref(n)) == S.EINVAL
@@ -75,6 +79,14 @@ def test_topology_workspace(L):
     assert L.workspace_size(C.byref(_p()), C.byref(a)) == 0
     assert L.workspace_size(C.byref(_p(topo=S.TOPO_SIMPLE)), C.byref(b)) == 0
     assert b.value - a.value >= 64 * 48 * 8 + 1000
+
+
+def test_psf_workspace(L):
+    """The deconvolving model adds (max_labels + 4) images of fp32."""
+    a, b = C.c_size_t(0), C.c_size_t(0)
+    assert L.workspace_size(C.byref(_p(max_labels=3)), C.byref(a)) == 0
+    assert L.workspace_size(C.byref(_p(max_labels=3, psf_sigma=2.0)), C.byref(b)) == 0
+    assert b.value - a.value >= 64 * 48 * 4 * 7
 
 
 def test_call_order_and_nulls(L):
