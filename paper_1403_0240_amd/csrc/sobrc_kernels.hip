@@ -1798,6 +1798,7 @@ __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img
 
 constexpr unsigned long long kKeyInf = 0xFFFFFFFFFFFFull;  // 48-bit key of a pixel with no undecided candidate
 constexpr int kTopoBox = 1000;                            // 10^3 box (3D); 18^2 = 324 in 2D
+constexpr int kTopoCand = 512;                            // candidates of a tile staged in LDS
 // per-iteration tile stamp, odd so that a cleared mark (0) never matches
 __device__ __forceinline__ unsigned topo_stamp(unsigned it) { return (it << 1) | 1u; }
 
@@ -1921,9 +1922,19 @@ __device__ __forceinline__ void word_store(unsigned long long* p, unsigned long 
 // Decide what can be decided of tile t from the per-pixel words of the tile
 // and its halo, in local rounds on LDS; the tile's own words are written
 // back.  Returns (block-uniform) whether undecided candidates remain.
+// A tile's undecided candidates during its local rounds (LDS).
+struct TopoCand {
+    unsigned n;
+    unsigned p[kTopoCand];              // record index
+    unsigned rw[kTopoCand];             // a | b << 16
+    unsigned long long key[kTopoCand];  // rank key
+    unsigned short cell[kTopoCand];     // box cell
+    unsigned char st[kTopoCand];        // 1 undecided, 2 executed, 3 refused
+};
+
 template <int ND>
 __device__ bool topo_tile(const Geom& g, const Bufs& b, int cur, unsigned t, const float* __restrict__ grad,
-                          unsigned long long* words, unsigned short* s_lab, unsigned long long* s_key)
+                          unsigned long long* words, unsigned short* s_lab, unsigned long long* s_key, TopoCand& C)
 {
     using M = NbBits<ND>;
     const TileInfo ti = tile_info(g, t);
@@ -1996,7 +2007,61 @@ __device__ bool topo_tile(const Geom& g, const Bufs& b, int cur, unsigned t, con
             s_key[(lx + 1) + ti.BX * ((ly + 1) + ti.BY * (lz + ti.hz))] = kKeyInf;
         }
     };
+    // the tile's undecided candidates, staged in LDS when they fit
+    if (threadIdx.x == 0)
+        C.n = 0;
+    __syncthreads();
+    for (unsigned p = r0 + threadIdx.x; p < r1; p += kBlock)
+        if (b.tstate[p] == 1) {
+            const unsigned j = atomicAdd(&C.n, 1u);
+            if (j < (unsigned)kTopoCand) {
+                const uint2 r = rec[p];
+                C.p[j] = p;
+                C.cell[j] = (unsigned short)cell_of(r.x);
+                C.rw[j] = r.y;
+                C.key[j] = cand_key(grad[p], (int)(r.y >> 16));
+                C.st[j] = 1;
+            }
+        }
+    __syncthreads();
+    const unsigned nc = C.n;
     int pend = 0;
+    if (nc <= (unsigned)kTopoCand) {
+        for (;;) {
+            int prog = 0;
+            for (unsigned j = threadIdx.x; j < nc; j += kBlock)
+                if (C.st[j] == 1) {
+                    const unsigned char d = decide(C.rw[j], C.cell[j], C.key[j]);
+                    if (d) {
+                        C.st[j] = d;
+                        prog = 1;
+                    }
+                }
+            if (!__syncthreads_or(prog))
+                break;
+            clear_own_keys();
+            __syncthreads();
+            for (unsigned j = threadIdx.x; j < nc; j += kBlock)
+                if (C.st[j] == 1)
+                    atomicMin(&s_key[C.cell[j]], C.key[j]);
+            __syncthreads();
+        }
+        // states back; words of the candidates' pixels published (the other
+        // pixels of the tile kept theirs)
+        for (unsigned j = threadIdx.x; j < nc; j += kBlock) {
+            const unsigned p = C.p[j];
+            const unsigned char st = C.st[j];
+            pend |= st == 1;
+            if (st != 1)
+                b.tstate[p] = st;
+            int x, y, z;
+            unpack(g, rec[p].x, x, y, z);
+            const int c = C.cell[j];
+            word_store(words + lin_of(g, x, y, z), (s_key[c] << 16) | s_lab[c]);
+        }
+        return __syncthreads_or(pend) != 0;
+    }
+    // many candidates: states kept in memory
     for (;;) {
         int prog = 0;
         for (unsigned p = r0 + threadIdx.x; p < r1; p += kBlock) {
@@ -2080,6 +2145,7 @@ __global__ __launch_bounds__(kBlock) void k_topo_round(Geom g, Bufs b, int cur, 
 {
     __shared__ unsigned short s_lab[kTopoBox];
     __shared__ unsigned long long s_key[kTopoBox];
+    __shared__ TopoCand s_cand;
     DevState* ds = b.ds;
     if (stopped(ds))
         return;
@@ -2094,7 +2160,7 @@ __global__ __launch_bounds__(kBlock) void k_topo_round(Geom g, Bufs b, int cur, 
     unsigned* next = b.tlist[(r + 1) & 1];
     for (unsigned i = L; i < n; i += G) {
         const unsigned t = list[i];
-        const bool pend = topo_tile<ND>(g, b, cur, t, grad, b.pmap, s_lab, s_key);
+        const bool pend = topo_tile<ND>(g, b, cur, t, grad, b.pmap, s_lab, s_key, s_cand);
         if (pend && threadIdx.x == 0)
             next[atomicAdd(&ds->topo_cnt[r + 1], 1u)] = t;
         __syncthreads();  // LDS reuse by the next tile
@@ -2110,6 +2176,7 @@ __global__ __launch_bounds__(kBlock) void k_topo_finish(Geom g, Bufs b, int cur,
 {
     __shared__ unsigned short s_lab[kTopoBox];
     __shared__ unsigned long long s_key[kTopoBox];
+    __shared__ TopoCand s_cand;
     __shared__ unsigned s_mk;
     DevState* ds = b.ds;
     if (stopped(ds))
@@ -2139,7 +2206,7 @@ __global__ __launch_bounds__(kBlock) void k_topo_finish(Geom g, Bufs b, int cur,
             if (mk == done)
                 continue;
             any = true;
-            const bool pend = topo_tile<ND>(g, b, cur, t, grad, b.pmap, s_lab, s_key);
+            const bool pend = topo_tile<ND>(g, b, cur, t, grad, b.pmap, s_lab, s_key, s_cand);
             __syncthreads();
             if (threadIdx.x == 0 && !pend)
                 b.tmark[t] = done;
