@@ -1121,6 +1121,8 @@ __device__ __forceinline__ float poisson_move(float v, float m_a, float m_b)
     return (jb - ja) - v * (logf(jb) - logf(ja));
 }
 
+// PSF: the deconvolving model (a compile-time switch keeps the plain path lean)
+template <bool PSF>
 __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const void* img, int cur, float* __restrict__ out, int gated, VB vb)
 {
     DevState* ds = b.ds;
@@ -1159,7 +1161,7 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
         SOBRC_FACE(z + 1 < g.nz, i + nxy)
 #undef SOBRC_FACE
         float dext;
-        if (g.psf) {
+        if (PSF) {
             // deconvolving model: delta^2 N(x) - 2 delta C(x), theta held fixed
             const float d = (float)(b.dtheta[bl] - b.dtheta[a]);
             dext = d * d * b.dN[i] - 2.f * d * b.dC[i];
@@ -1206,10 +1208,11 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
     }
 }
 
+template <bool PSF>
 __global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* img, int cur, float* __restrict__ out,
                                                   int gated)
 {
-    l2diff_body(g, b, img, cur, out, gated, VB{blockIdx.x, gridDim.x});
+    l2diff_body<PSF>(g, b, img, cur, out, gated, VB{blockIdx.x, gridDim.x});
 }
 
 // ------------------------------------------------- Sobolev update, Eq. (6)
@@ -1651,6 +1654,8 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, Sob
 // Region statistics follow exactly (integer deltas): per-block partials for
 // few labels, wave-merged atomics otherwise.  Tiles within one pixel of a
 // flip are marked dirty for the particle-set update.
+// TOPO: the moves were decided by the ranked acceptance (compile-time switch)
+template <bool TOPO>
 __device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const void* img, int cur, const float* __restrict__ grad_sob, const float* __restrict__ grad_l2, int flags, VB vb)
 {
     __shared__ long long s_dn[kSmallM], s_dq[kSmallM];
@@ -1666,7 +1671,7 @@ __device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const vo
         s_f = 0;
         s_rv = 0;
     }
-    if (g.topo && vb.id == 0 && threadIdx.x <= (unsigned)kTopoRounds)
+    if (TOPO && vb.id == 0 && threadIdx.x <= (unsigned)kTopoRounds)
         ds->topo_cnt[threadIdx.x] = 0;  // the ranked acceptance of this step is done
     __syncthreads();
     const unsigned n = ds->n[cur];
@@ -1685,7 +1690,7 @@ __device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const vo
         if (p < p1) {
             uint2 r;
             bool mv;
-            if (g.topo) {
+            if (TOPO) {
                 // decided by the ranked acceptance; its per-pixel words are cleared here
                 const unsigned char st = b.tstate[p];
                 r = rec[p];
@@ -1769,11 +1774,12 @@ __device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const vo
     }
 }
 
+template <bool TOPO>
 __global__ __launch_bounds__(kBlock) void k_flip(Geom g, Bufs b, const void* img, int cur,
                                                 const float* __restrict__ grad_sob,
                                                 const float* __restrict__ grad_l2, int flags)
 {
-    flip_body(g, b, img, cur, grad_sob, grad_l2, flags, VB{blockIdx.x, gridDim.x});
+    flip_body<TOPO>(g, b, img, cur, grad_sob, grad_l2, flags, VB{blockIdx.x, gridDim.x});
 }
 
 // ------------------------------------- ranked acceptance, topological control
@@ -2370,7 +2376,10 @@ hipError_t launch_stats_init(const Geom& g, const Bufs& b, const void* img, hipS
 hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur, float* out, int gated,
                          hipStream_t s)
 {
-    hipLaunchKernelGGL(k_l2diff, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, out, gated);
+    if (g.psf)
+        hipLaunchKernelGGL(k_l2diff<true>, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, out, gated);
+    else
+        hipLaunchKernelGGL(k_l2diff<false>, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, out, gated);
     return hipGetLastError();
 }
 
@@ -2400,7 +2409,10 @@ hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur,
 hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,
                        const float* grad_l2, int flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_flip, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, grad, grad_l2, flags);
+    if (g.topo)
+        hipLaunchKernelGGL(k_flip<true>, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, grad, grad_l2, flags);
+    else
+        hipLaunchKernelGGL(k_flip<false>, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, grad, grad_l2, flags);
     return hipGetLastError();
 }
 
@@ -2532,7 +2544,7 @@ __global__ __launch_bounds__(kBlock) void kb_l2diff(const ImgDesc* __restrict__ 
         const ImgDesc& D = d[i];
         const unsigned v = item - off[i];
         if (v < (unsigned)D.g.gp)
-            l2diff_body(D.g, D.b, D.img, (int)par[i], D.b.dE, 1, VB{v, (unsigned)D.g.gp});
+            l2diff_body<false>(D.g, D.b, D.img, (int)par[i], D.b.dE, 1, VB{v, (unsigned)D.g.gp});
     }
 }
 
@@ -2582,7 +2594,7 @@ __global__ __launch_bounds__(kBlock) void kb_flip(const ImgDesc* __restrict__ d,
         const ImgDesc& D = d[i];
         const unsigned v = item - off[i];
         if (v < (unsigned)D.g.gp)
-            flip_body(D.g, D.b, D.img, (int)par[i], l2 ? D.b.dE : D.b.gH1, D.b.dE, flags,
+            flip_body<false>(D.g, D.b, D.img, (int)par[i], l2 ? D.b.dE : D.b.gH1, D.b.dE, flags,
                       VB{v, (unsigned)D.g.gp});
         __syncthreads();
     }

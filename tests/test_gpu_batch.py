@@ -181,3 +181,27 @@ def test_launch_shapes_do_not_change_results(dims):
         assert S.run(ref, total, 0.0, S.MODE_SOBOLEV) == total
         assert_same(snapshot(c), snapshot(ref), f"after {total} iterations over several shapes")
     B.close()
+
+
+def test_batch_mixes_likelihoods():
+    """Slots with Poisson noise and the piecewise-smooth model run in the same
+    batch as Gaussian piecewise-constant slots, each equal to its own run."""
+    ws = [W.random_multilabel(22, (30, 34), 3, E=6.0, lam=0.5, model=W.PS, ps_radius=3, noise=W.POISSON),
+          W.random_multilabel(23, (27, 41), 3, E=6.0, lam=0.7, noise=W.POISSON),
+          W.blobs2d(210, side_lo=40, side_hi=120, E=6.0)]
+    print(f"[batch likelihood mix n={len(ws)}]", flush=True)
+    iters = 7
+    solo = []
+    for w in ws:
+        ctx, _, _ = make_ctx(w)
+        assert S.run(ctx, iters, 0.0, S.MODE_SOBOLEV) == iters
+        solo.append(snapshot(ctx))
+    B = S.Batch(len(ws))
+    ctxs = [make_ctx(w)[0] for w in ws]
+    for k, c in enumerate(ctxs):
+        B.set(k, c)
+    done = B.run(iters, 0.0, S.MODE_SOBOLEV)
+    assert all(done == iters)
+    for k, c in enumerate(ctxs):
+        assert_same(snapshot(c), solo[k], f"slot of image {k}")
+    B.close()
