@@ -73,7 +73,8 @@ def footprint(w, capacity: int) -> int:
     plus the image."""
     p = S.make_params(w.image.shape, str(w.image.dtype), w.E, w.lam, model=w.model,
                       ps_radius=w.ps_radius, eps=w.eps, max_labels=w.max_labels,
-                      max_particles=capacity)
+                      max_particles=capacity, noise=getattr(w, "noise", 0),
+                      topo=getattr(w, "topo", 0), psf_sigma=getattr(w, "psf_sigma", 0.0))
     return S.workspace_size(p) + w.image.nbytes
 
 
@@ -104,6 +105,10 @@ class Server:
         return time.perf_counter() - self.t0
 
     def submit(self, req: Request):
+        if getattr(req.work, "topo", 0) or getattr(req.work, "psf_sigma", 0.0) > 0.0:
+            # such contexts are not batched: run them with sobrc.run on their own
+            raise ValueError(f"request {req.rid}: topological control and the deconvolving model "
+                             f"are not served in batches")
         req.footprint = footprint(req.work, default_capacity(req.work))
         if req.footprint > self.budget:
             raise ValueError(f"request {req.rid} needs {req.footprint} bytes > budget {self.budget}")

@@ -70,3 +70,18 @@ def test_each_result_same_alone_and_in_mix(realtime):
         assert r.latency > 0
     stats = SV.latency_stats(done)
     assert stats["p99_s"] >= stats["p50_s"] > 0
+
+
+def test_unbatchable_requests_are_refused():
+    """Topological control and the deconvolving model are not batched; the
+    server says so at submission instead of failing inside a tick."""
+    srv = SV.Server(hbm_budget=1 << 30, slots=4)
+    w = W.blobs2d(401, side_lo=48, side_hi=64, square=True)
+    w.topo = S.TOPO_SIMPLE
+    with pytest.raises(ValueError):
+        srv.submit(SV.Request(0, w, 0.0))
+    w = W.blobs2d(402, side_lo=48, side_hi=64, square=True)
+    w.psf_sigma = 2.0
+    with pytest.raises(ValueError):
+        srv.submit(SV.Request(1, w, 0.0))
+    assert not srv.waiting
