@@ -101,3 +101,27 @@ def test_psf_contexts_are_not_batched():
         assert e.value.code == S.EINVAL
     finally:
         batch.close()
+
+
+def test_deconv_with_topological_control(ora):
+    """The deconvolving gradient driving the ranked, controlled acceptance:
+    trajectory against the oracle until the first marginal decision."""
+    from test_gpu_topology import MARGIN, topo_marginal
+    w = _case(58, (36, 44), 2.0, n_labels=3, lam=0.2)
+    w.topo = S.TOPO_SIMPLE
+    print("[case deconv + topo]", flush=True)
+    P = ora.params_of(w)
+    ctx, img, lab = gpu_state(w)
+    L_o = w.labels.copy()
+    for t in range(8):
+        L_next, info = ora.step(P, w.image, L_o, ora.MODE_SOBOLEV)
+        S.step(ctx, S.MODE_SOBOLEV)
+        L_g = S.get_labels(ctx).cpu().numpy()
+        diff = L_g != L_next
+        if diff.any():
+            g = info["dE_h1"]
+            marg = topo_marginal(w.labels.shape, info["lin"], g, MARGIN * np.abs(g).max())
+            assert not (diff & ~marg).any(), f"step {t}: non-marginal differences"
+            print(f"  step {t}: {int(diff.sum())} marginal differences; stopping comparison")
+            return
+        L_o = L_next
