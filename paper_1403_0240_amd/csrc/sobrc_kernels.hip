@@ -1471,10 +1471,9 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
         const int kx0 = bx0 / S::TX, nkx = (bx1 - 1) / S::TX - kx0 + 1;
         const int ky0 = by0 / S::TY, nky = (by1 - 1) / S::TY - ky0 + 1;
         const int kz0 = bz0 / S::TZ, nkz = (bz1 - 1) / S::TZ - kz0 + 1;
-        const int nnt = nkx * nky * nkz;
-        const int kown = (tx - kx0) + nkx * ((ty - ky0) + nky * (tz - kz0));
+        // neighbour tiles k = kxi + 3 (kyi + 3 kzi), kxi < nkx, kyi < nky, kzi < nkz
+        const int kown = (tx - kx0) + 3 * ((ty - ky0) + 3 * (tz - kz0));
         const int BYe = by1 - by0, BZe = bz1 - bz0;
-        const int nrt = nkx * BYe * BZe;  // box rows per x-tile: (x-tile, y, z) row tasks
         __syncthreads();  // the previous tile is done with LDS
         // Round trip 1: every load this tile needs except the L2 gradients,
         // issued together.  Row task ri = (x-tile, box y, box z) follows from
@@ -1487,9 +1486,12 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
             const int ri = (int)threadIdx.x + q * kSobBlock;
             r_beg[q] = r_end[q] = r_word[q] = r_pre[q] = 0u;
             r_cell[q] = r_lx0[q] = r_lx1[q] = r_xb[q] = r_row[q] = 0;
-            if (ri < nrt) {
-                const int kxi = ri % nkx, rest = ri / nkx;
-                const int y = by0 + rest % BYe, z = bz0 + rest / BYe;
+            // ri = kxi + 3 (yi + BY zi): compile-time strides, no division
+            // by the box's runtime extents
+            const int kxi = ri % 3, rest = ri / 3;
+            const int yi = rest % S::BY, zi = rest / S::BY;
+            if (kxi < nkx && yi < BYe && zi < BZe) {
+                const int y = by0 + yi, z = bz0 + zi;
                 const int kx = kx0 + kxi, ky = y / S::TY, kz = z / S::TZ;
                 const unsigned tile = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
                 const int row = (y - ky * S::TY) + S::TY * (z - kz * S::TZ);
@@ -1509,8 +1511,9 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
         // tile's own rows for the core list
         unsigned hdr = 0u, nb_beg = 0u, nb_end = 0u, own_word = 0u, own_pre = 0u;
         if (threadIdx.x < 64) {
-            if (lane < nnt) {
-                const int kx = kx0 + lane % nkx, ky = ky0 + (lane / nkx) % nky, kz = kz0 + lane / (nkx * nky);
+            const int kxi = lane % 3, kyi = (lane / 3) % 3, kzi = lane / 9;
+            if (kxi < nkx && kyi < nky && kzi < nkz) {
+                const int kx = kx0 + kxi, ky = ky0 + kyi, kz = kz0 + kzi;
                 const unsigned tile = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
                 nb_beg = ts[tile];
                 nb_end = ts[tile + 1];
