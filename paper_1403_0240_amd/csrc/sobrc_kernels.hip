@@ -2108,8 +2108,8 @@ __device__ bool topo_tile(const Geom& g, const Bufs& b, int cur, unsigned t, con
     return __syncthreads_or(pend) != 0;
 }
 
-// Candidates of state t: state, per-pixel smallest key, and the list of tiles
-// holding candidates (round 0's work).
+// Candidates of state t: state, per-pixel smallest key, and the stamp of the
+// tiles holding candidates (round 0's work).
 __global__ __launch_bounds__(kBlock) void k_topo_prep(Geom g, Bufs b, int cur, const float* __restrict__ grad_sob,
                                                      const float* __restrict__ grad_l2, int flags)
 {
@@ -2136,15 +2136,17 @@ __global__ __launch_bounds__(kBlock) void k_topo_prep(Geom g, Bufs b, int cur, c
             }
         }
         // records are tile-sorted: the first candidate lane of each run of
-        // one tile lists it, the tile's stamp keeps it listed once
+        // one tile stamps it (round 0 walks the non-empty tiles and takes
+        // the stamped ones)
         const unsigned prev = __shfl_up(tile, 1);
-        if (tile != 0xFFFFFFFFu && (lane_id() == 0 || prev != tile) && atomicExch(&b.tmark[tile], stamp) != stamp)
-            b.tlist[0][atomicAdd(&ds->topo_cnt[0], 1u)] = tile;
+        if (tile != 0xFFFFFFFFu && (lane_id() == 0 || prev != tile))
+            b.tmark[tile] = stamp;
     }
 }
 
-// Round r: the tiles listed by round r - 1 (by the preparation for r = 0);
-// those with undecided candidates left are listed for round r + 1.  The
+// Round r: the tiles listed by round r - 1 (for r = 0 the non-empty tiles
+// the preparation stamped); those with undecided candidates left are listed
+// for round r + 1.  The
 // per-pixel words are updated in place: a block may see a neighbour's words
 // from before or after that neighbour's work in this round, and either is a
 // valid state of those pixels for every decision taken from it.
@@ -2158,17 +2160,21 @@ __global__ __launch_bounds__(kBlock) void k_topo_round(Geom g, Bufs b, int cur, 
     DevState* ds = b.ds;
     if (stopped(ds))
         return;
-    const unsigned n = ds->topo_cnt[r];
+    // round 0: the non-empty tiles, those stamped by the preparation
+    const unsigned n = r == 0 ? ds->n_active[cur] : ds->topo_cnt[r];
+    const unsigned stamp = topo_stamp(ds->iters);
     // consecutive list entries (neighbouring tiles, mostly) on one XCD
     const unsigned G = gridDim.x;
     const unsigned L = (G & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);
     if (L >= n)
         return;
     const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
-    const unsigned* list = b.tlist[r & 1];
+    const unsigned* list = r == 0 ? b.active[cur] : b.tlist[r & 1];
     unsigned* next = b.tlist[(r + 1) & 1];
     for (unsigned i = L; i < n; i += G) {
         const unsigned t = list[i];
+        if (r == 0 && b.tmark[t] != stamp)
+            continue;  // no candidate in this tile
         const bool pend = topo_tile<ND>(g, b, cur, t, grad, b.pmap, s_lab, s_key, s_cand);
         if (pend && threadIdx.x == 0)
             next[atomicAdd(&ds->topo_cnt[r + 1], 1u)] = t;
