@@ -145,8 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_deconv_normal(Geom g, Bufs b, const 
     }
 }
 
-// theta: the partial sums folded, the system restricted to the labels that
-// have pixels (the others get 0), solved by elimination with partial pivoting.
+// theta: the partial sums folded, the labels without pixels set to 0, the
+// normal equations solved by elimination.
 __global__ __launch_bounds__(kBlock) void k_deconv_solve(Geom g, Bufs b, int nblocks)
 {
     __shared__ double s_part[kBlock / 64][kDeconvSums];
@@ -181,62 +181,55 @@ __global__ __launch_bounds__(kBlock) void k_deconv_solve(Geom g, Bufs b, int nbl
     __syncthreads();
     if (threadIdx.x != 0)
         return;
+    // the kDeconvM x kDeconvM system with identity rows for absent labels
+    // (theta 0 there), eliminated with every index known at compile time
     const int M = g.max_labels;
-    int idx[kDeconvM], lab[kDeconvM], n = 0;
-    for (int l = 0; l < kDeconvM; ++l) {
-        idx[l] = -1;
-        if (l < M && b.st_n[l] > 0) {
-            idx[l] = n;
-            lab[n++] = l;
-        }
-    }
-    double A[kDeconvM][kDeconvM], c[kDeconvM], t[kDeconvM];
-    int j = 0;
+    bool present[kDeconvM];
+#pragma unroll
     for (int l = 0; l < kDeconvM; ++l)
-        for (int m = l; m < kDeconvM; ++m, ++j)
-            if (idx[l] >= 0 && idx[m] >= 0)
-                A[idx[l]][idx[m]] = A[idx[m]][idx[l]] = s_sum[j];
+        present[l] = l < M && b.st_n[l] > 0;
+    double A[kDeconvM][kDeconvM], c[kDeconvM];
+    int j = 0;
+#pragma unroll
+    for (int l = 0; l < kDeconvM; ++l)
+#pragma unroll
+        for (int m = l; m < kDeconvM; ++m, ++j) {
+            const double v = present[l] && present[m] ? s_sum[j] : (l == m ? 1.0 : 0.0);
+            A[l][m] = v;
+            A[m][l] = v;
+        }
+#pragma unroll
     for (int l = 0; l < kDeconvM; ++l, ++j)
-        if (idx[l] >= 0)
-            c[idx[l]] = s_sum[j];
-    bool ok = n > 0;
-    for (int col = 0; col < n && ok; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < n; ++r)
-            if (fabs(A[r][col]) > fabs(A[piv][col]))
-                piv = r;
-        if (A[piv][col] == 0.0) {
-            ok = false;
-            break;
-        }
-        if (piv != col) {
-            for (int q = 0; q < n; ++q) {
-                const double tmp = A[col][q];
-                A[col][q] = A[piv][q];
-                A[piv][q] = tmp;
-            }
-            const double tmp = c[col];
-            c[col] = c[piv];
-            c[piv] = tmp;
-        }
-        for (int r = col + 1; r < n; ++r) {
-            const double f = A[r][col] / A[col][col];
-            for (int q = col; q < n; ++q)
+        c[l] = present[l] ? s_sum[j] : 0.0;
+    bool ok = false;
+#pragma unroll
+    for (int l = 0; l < kDeconvM; ++l)
+        ok = ok || present[l];
+    // symmetric positive (semi)definite: elimination in order, pivots checked
+#pragma unroll
+    for (int col = 0; col < kDeconvM; ++col) {
+        ok = ok && A[col][col] != 0.0;
+        const double inv = ok ? 1.0 / A[col][col] : 0.0;
+#pragma unroll
+        for (int r = col + 1; r < kDeconvM; ++r) {
+            const double f = A[r][col] * inv;
+#pragma unroll
+            for (int q = col; q < kDeconvM; ++q)
                 A[r][q] -= f * A[col][q];
             c[r] -= f * c[col];
         }
     }
-    for (int r = n - 1; r >= 0 && ok; --r) {
+    double t[kDeconvM];
+#pragma unroll
+    for (int r = kDeconvM - 1; r >= 0; --r) {
         double acc = c[r];
-        for (int q = r + 1; q < n; ++q)
+#pragma unroll
+        for (int q = r + 1; q < kDeconvM; ++q)
             acc -= A[r][q] * t[q];
-        t[r] = acc / A[r][r];
+        t[r] = ok ? acc / A[r][r] : 0.0;
     }
     for (int l = 0; l < M; ++l)
-        b.dtheta[l] = 0.0;
-    if (ok)
-        for (int q = 0; q < n; ++q)
-            b.dtheta[lab[q]] = t[q];
+        b.dtheta[l] = ok && present[l] ? t[l] : 0.0;
 }
 
 // R = I - J with J = sum_l theta_l u_l.
