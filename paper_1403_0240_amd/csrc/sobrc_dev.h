@@ -74,7 +74,7 @@ constexpr unsigned kErrInput = 4u;
 constexpr unsigned kErrTopo = 8u;  // ranked acceptance did not finish within kTopoMaxPasses
 
 // Parallel rounds of the ranked acceptance before one block finishes the rest.
-constexpr int kTopoRounds = 24;
+constexpr int kTopoRounds = 16;
 constexpr int kTopoMaxPasses = 4096;  // passes of the finishing block over the tiles left
 
 // Problem geometry and parameters, passed by value to every kernel.
