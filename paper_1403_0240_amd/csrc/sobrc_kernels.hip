@@ -1392,6 +1392,15 @@ struct BrickShape {
     static constexpr int SX = BX | 1;
     static constexpr int NCELL = SX * BY * BZ;
     static constexpr int LIM = (H + 1) * (H + 1);
+    // half-width of the support in box row (dy, dz) when the support is
+    // d^2 < (H + 1)^2: the largest k with k^2 + dy^2 + dz^2 < LIM, -1 if none
+    static constexpr int full_w(int dy, int dz)
+    {
+        int w = -1;
+        while (w + 1 <= H && (w + 1) * (w + 1) + dy * dy + dz * dz < LIM)
+            ++w;
+        return w;
+    }
     static constexpr int count()
     {
         int n = 0;
@@ -1623,8 +1632,12 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
 #pragma unroll
                 for (int dy = -H; dy <= H; ++dy) {
                     // a row outside the support (w < 0) gets an empty window: no branch,
-                    // so the row reads of one particle issue together
-                    const int w = sw.rw[(dy + H) + (2 * H + 1) * (dz + S::HZ)];
+                    // so the row reads of one particle issue together.  With every
+                    // offset of the box inside the support (FULL) the half-widths
+                    // are compile-time constants and empty rows are not read.
+                    if (FULL && S::full_w(dy, dz) < 0)
+                        continue;
+                    const int w = FULL ? S::full_w(dy, dz) : sw.rw[(dy + H) + (2 * H + 1) * (dz + S::HZ)];
                     const unsigned wm = w >= 0 ? (2u << (2 * w)) - 1u : 0u;
                     const uint2 m = s_m[row0 + (dy + H) + S::BY * (dz + S::HZ)];
                     const unsigned win = wm << (lx + H - (w >= 0 ? w : 0));
