@@ -534,16 +534,19 @@ __device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restr
 }
 
 // Write the records of tile t (counted by wave_count_tile) at rec[o...], one
-// wave, canonical order: position inside the tile (x fastest), then b.
+// wave, canonical order: position inside the tile (x fastest), then b.  The
+// caller loads the tile slot's header (hdr = slot[0]) and this lane's row word
+// (slot[1 + lane], every lane: the slot has kSlotWords > 64 words) together
+// with the tile's offset, so that their latencies overlap.
 __device__ void wave_write_tile(const Geom& g, const unsigned short* __restrict__ lab, unsigned t, WaveEmit& W,
-                                const unsigned* __restrict__ slot, uint2* __restrict__ rec, unsigned o)
+                                unsigned hdr, unsigned word, uint2* __restrict__ rec, unsigned o)
 {
+    static_assert(kSlotWords > 64, "a row word per lane");
     const int lane = lane_id();
     TileInfo ti = tile_info(g, t);
-    const unsigned hdr = slot[0];
     if ((hdr & 0xffffu) != 0xffffu) {
         const unsigned lo = hdr & 0xffffu, hi = hdr >> 16;
-        unsigned word = lane < ti.TY * ti.TZ ? slot[1 + lane] : 0u;
+        word = lane < ti.TY * ti.TZ ? word : 0u;
         unsigned pb = word & 0xffffu, own_lo = word >> 16;
         unsigned tot;
         unsigned oo = o + wave_excl_scan_u((unsigned)__popc(pb), tot);
@@ -621,20 +624,24 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     __shared__ WaveEmit W[kBlock / 64];
     __shared__ unsigned s_dl[kBlock];
     __shared__ unsigned s_ndl;
+    const unsigned G = vb.n;
+    const unsigned j = vb.id + threadIdx.x * G;  // G * kBlock >= 8 * ceil(ntiles / 8)
+    unsigned t;
+    const bool has = slot_tile(g, j, t);
+    // the tile's loads go out with the stop flag (in bounds either way)
+    const unsigned tdv = has ? b.dirty[t] : 0u;
+    const unsigned ts0 = has ? b.tstart[cur][t] : 0u, ts1 = has ? b.tstart[cur][t + 1] : 0u;
     if (gated && stopped(b.ds))
         return;
     const unsigned epoch = b.ds->epoch;
-    const unsigned G = vb.n;
     if (threadIdx.x == 0)
         s_ndl = 0;
     __syncthreads();
-    const unsigned j = vb.id + threadIdx.x * G;  // G * kBlock >= 8 * ceil(ntiles / 8)
-    unsigned t;
-    if (slot_tile(g, j, t)) {
-        if (tile_dirty(b, t, epoch, all_dirty)) {
+    if (has) {
+        if (all_dirty || tdv == epoch) {
             s_dl[atomicAdd(&s_ndl, 1u)] = t;
         } else {
-            unsigned c = b.tstart[cur][t + 1] - b.tstart[cur][t];
+            unsigned c = ts1 - ts0;
             b.tcnt[t] = c;
             if (c) {
                 atomicAdd(&b.part_cnt[t >> g.lgRe], c);
@@ -675,21 +682,22 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
 // forms the exclusive prefix of the per-block list lengths (two 16-byte loads
 // per thread) and the waves of all blocks take list items round-robin, so a
 // cluster of dirty tiles in one emission block no longer serialises on its
-// four waves.  The items also go to a flat list (positions in the per-block
-// lists) for the write kernel.
+// four waves.  The items also go to a flat list (tile ids) for the write
+// kernel.
 template <int ND>
 __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, int gated, VB vb)
 {
     __shared__ WaveEmit W[kBlock / 64];
     __shared__ unsigned s_pre[kMaxGrid + 1];
     __shared__ unsigned s_red[kBlock / 64];
-    if (gated && stopped(b.ds))
-        return;
     static_assert(kMaxGrid == 8 * kBlock, "eight list lengths per thread");
     const int ge = g.ge;
     const int i0 = (int)threadIdx.x * 8;
     const uint4* dc = (const uint4*)b.dcnt;  // kMaxGrid entries; those >= ge are ignored
+    // the list lengths are loaded with the stop flag (in bounds either way)
     const uint4 q0 = dc[2 * threadIdx.x], q1 = dc[2 * threadIdx.x + 1];
+    if (gated && stopped(b.ds))
+        return;
     unsigned c[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
     unsigned sum = 0;
 #pragma unroll
@@ -724,7 +732,7 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
         const unsigned td = b.dlist[pos];
         unsigned cc = wave_count_tile<ND>(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
-            b.dflat[item] = pos;
+            b.dflat[item] = td;
             b.tcnt[td] = cc;
             if (cc) {
                 atomicAdd(&b.part_cnt[td >> g.lgRe], cc);
@@ -751,48 +759,76 @@ __device__ __forceinline__ T wave_sum(T v)
 // Single block: fold the flip partials into the region statistics, refresh the
 // per-label table of the L2 gradient, scan the emission partials into block
 // offsets, check the capacity (requesting a roll-back if it is exceeded), and
-// record telemetry and the convergence test.
+// record telemetry and the convergence test.  The block is latency bound: all
+// partials are loaded before the first wait (the first two emission partials
+// of each thread stay in registers), and the per-label statistics partials are
+// split over every wave, kScanThreads / 64 / max_labels waves per label.
 __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur, int nxt, int is_init, float tol, int32_t* d_nflips, int gated, int flags, VB vb)
 {
-    __shared__ unsigned long long s_sum[kScanThreads / 64];
-    __shared__ unsigned s_nz[kScanThreads / 64];
-    __shared__ unsigned s_f[kScanThreads / 64], s_r[kScanThreads / 64];
+    constexpr int kW = kScanThreads / 64;
+    static_assert(kMaxGrid <= 2 * kScanThreads, "two flip partials per thread");
+    __shared__ unsigned long long s_sum[kW];
+    __shared__ unsigned s_nz[kW];
+    __shared__ unsigned s_f[kW], s_r[kW];
+    __shared__ long long s_dn[kW], s_dq[kW];
     DevState* ds = b.ds;
     if (gated && stopped(ds))
         return;
     const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    // every load is issued up front; the work below waits on them once
     const int per = (g.ge + kScanThreads - 1) / kScanThreads;  // emission partials per thread (<= 2 typ.)
     const int i0 = tid * per, i1 = min(i0 + per, g.ge);
-    unsigned long long sum = 0;
-    unsigned nz = 0;
-    for (int i = i0; i < i1; ++i) {
-        sum += b.part_cnt[i];
-        nz += b.part_act[i];
-    }
+    const bool has0 = i0 < i1, has1 = i0 + 1 < i1;
+    const unsigned c0 = has0 ? b.part_cnt[i0] : 0u, z0 = has0 ? b.part_act[i0] : 0u;
+    const unsigned c1 = has1 ? b.part_cnt[i0 + 1] : 0u, z1 = has1 ? b.part_act[i0 + 1] : 0u;
     unsigned f = 0, rv = 0;
-    long long dn = 0, dq = 0, n0 = 0, q0 = 0;
-    const bool label_wave = g.small_m && w < g.max_labels;
     if (!is_init) {
-        for (int i = tid; i < g.gp; i += kScanThreads) {
-            f += b.part_f[i];
-            rv += b.part_f[g.gp + i];
-        }
-        if (label_wave) {
-            const long long* pn = b.part_n + (long long)w * g.gp;
-            const long long* pq = b.part_q + (long long)w * g.gp;
-#pragma unroll 4
-            for (int i = lane; i < g.gp; i += 64) {
-                dn += pn[i];
-                dq += pq[i];
+        const int j1 = tid + kScanThreads;
+        f = (tid < g.gp ? b.part_f[tid] : 0u) + (j1 < g.gp ? b.part_f[j1] : 0u);
+        rv = (tid < g.gp ? b.part_f[g.gp + tid] : 0u) + (j1 < g.gp ? b.part_f[g.gp + j1] : 0u);
+    }
+    // statistics of few labels: wave w takes chunk cw of label lw
+    const int L = g.small_m ? g.max_labels : 0;
+    const int wpl = L ? kW / L : 0;
+    const int lw = (wpl && w < L * wpl) ? w / wpl : -1;
+    const int cw = wpl ? w % wpl : 0;
+    const bool lead = lw >= 0 && cw == 0 && lane == 0;
+    long long n0 = 0, q0 = 0, dn = 0, dq = 0;
+    if (lead) {
+        n0 = b.st_n[lw];
+        q0 = b.st_s1[lw];
+    }
+    unsigned pre_n = 0, pre_it = 0, pre_lm = 0, pre_sw = 0;
+    if (tid == 0 && !is_init) {
+        pre_n = ds->n[cur];
+        pre_it = ds->iters;
+        pre_lm = ds->lmode;
+        pre_sw = ds->switch_it;
+    }
+    if (!is_init && lw >= 0) {
+        const int lo = (int)((long long)cw * g.gp / wpl), hi = (int)((long long)(cw + 1) * g.gp / wpl);
+        const long long* pn = b.part_n + (long long)lw * g.gp;
+        const long long* pq = b.part_q + (long long)lw * g.gp;
+        for (int k0 = lo + lane; k0 < hi; k0 += 8 * 64) {
+            long long an[8], aq[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = k0 + 64 * u;
+                an[u] = i < hi ? pn[i] : 0;
+                aq[u] = i < hi ? pq[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                dn += an[u];
+                dq += aq[u];
             }
         }
     }
-    if (label_wave && lane == 0) {
-        n0 = b.st_n[w];
-        q0 = b.st_s1[w];
+    unsigned long long sum = (unsigned long long)c0 + c1;
+    unsigned nz = z0 + z1;
+    for (int i = i0 + 2; i < i1; ++i) {  // very large images only
+        sum += b.part_cnt[i];
+        nz += b.part_act[i];
     }
-    // flips, and statistics of few labels: one wave per label
     unsigned nf = 0;
     if (!is_init) {
         f = wave_sum(f);
@@ -802,20 +838,12 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
             s_r[w] = rv;
         }
     }
-    if (label_wave) {
+    if (!is_init && lw >= 0) {
         dn = wave_sum(dn);
         dq = wave_sum(dq);
         if (lane == 0) {
-            long long n = n0 + dn, q = q0 + dq;
-            if (!is_init) {
-                b.st_n[w] = n;
-                b.st_s1[w] = q;
-            }
-            double d = (double)n;
-            float mu = n > 0 ? (float)((double)q * g.fx_inv / d) : 0.f;
-            float fa = n > 1 ? (float)(d / (d - 1.0)) : 0.f;
-            float fb = (float)(d / (d + 1.0));
-            b.lstat[w] = make_float4(mu, fa, fb, 0.f);
+            s_dn[w] = dn;
+            s_dq[w] = dq;
         }
     }
     if (!g.small_m) {  // statistics already final (atomics in k_flip)
@@ -844,15 +872,31 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
         s_nz[w] = inz;
     }
     __syncthreads();
+    if (lead) {
+        long long n = n0, q = q0;
+        if (!is_init) {
+            for (int k = 0; k < wpl; ++k) {
+                n += s_dn[w + k];
+                q += s_dq[w + k];
+            }
+            b.st_n[lw] = n;
+            b.st_s1[lw] = q;
+        }
+        double d = (double)n;
+        float mu = n > 0 ? (float)((double)q * g.fx_inv / d) : 0.f;
+        float fa = n > 1 ? (float)(d / (d - 1.0)) : 0.f;
+        float fb = (float)(d / (d + 1.0));
+        b.lstat[lw] = make_float4(mu, fa, fb, 0.f);
+    }
     unsigned nb = 0;  // reversals
     if (!is_init)
-        for (int i = 0; i < kScanThreads / 64; ++i) {
+        for (int i = 0; i < kW; ++i) {
             nf += s_f[i];
             nb += s_r[i];
         }
     unsigned long long off = 0, total = 0;
     unsigned offz = 0, totz = 0;
-    for (int i = 0; i < kScanThreads / 64; ++i) {
+    for (int i = 0; i < kW; ++i) {
         off += i < w ? s_sum[i] : 0;
         offz += i < w ? s_nz[i] : 0;
         total += s_sum[i];
@@ -862,7 +906,8 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
     offz += inz - nz;
     const bool overflow = total > (unsigned long long)b.cap;
     for (int i = i0; i < i1; ++i) {
-        unsigned c = b.part_cnt[i], z = b.part_act[i];
+        const unsigned c = i == i0 ? c0 : (i == i0 + 1 ? c1 : b.part_cnt[i]);
+        const unsigned z = i == i0 ? z0 : (i == i0 + 1 ? z1 : b.part_act[i]);
         if (!overflow) {
             b.part_off[i] = (unsigned)off;
             b.part_aoff[i] = offz;
@@ -885,7 +930,7 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
             ds->need = total > 0xffffffffull ? 0xffffffffu : (unsigned)total;
             if (!is_init) {
                 ds->undo = 1;
-                ds->n[nxt] = ds->n[cur];
+                ds->n[nxt] = pre_n;
                 ds->n_active[nxt] = ds->n_active[cur];
             }
         } else {
@@ -896,7 +941,7 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
         if (!is_init) {
             ds->nflips = nf;
             if (!overflow) {
-                unsigned ncur = ds->n[cur], it = ds->iters;
+                const unsigned ncur = pre_n, it = pre_it;
                 b.hist[it % kHist] = ncur;
                 b.hist[kHist + it % kHist] = nf;
                 b.hist[2 * kHist + it % kHist] = nb;
@@ -910,7 +955,7 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
                 // gradients from the next step on
                 const bool osc = nf > 0u && 2ull * nb >= (unsigned long long)nf;
                 const bool cycle = nf > 0u && nb == nf;  // every flip undoes the previous step's
-                const unsigned lm = ds->lmode, sw = ds->switch_it;
+                const unsigned lm = pre_lm, sw = pre_sw;
                 // this step and the one before ran with L2 gradients
                 const bool l2_both = sw != 0u && sw <= it;
                 if ((flags & kAuto) && tol > 0.f && l2_both && cycle && (lm & 4u))
@@ -966,6 +1011,15 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     __shared__ unsigned s_dl[kBlock];
     __shared__ unsigned s_ndl;
     DevState* ds = b.ds;
+    // this thread's tile of range vb.id (< ge): its loads go out with the
+    // state flags (in bounds whichever way the flags decide)
+    const int t0 = vb.id << g.lgRe, t1 = min(t0 + g.Re, g.ntiles);
+    const int t = t0 + (int)threadIdx.x;
+    const bool in = t < t1;
+    const unsigned c = in ? b.tcnt[t] : 0;
+    const unsigned tdv = in ? b.dirty[t] : 0u;
+    const unsigned tso = in ? b.tstart[cur][t] : 0u;
+    const unsigned base = b.part_off[vb.id], abase = b.part_aoff[vb.id];
     if (ds->undo) {
         // the same gradients k_flip decided on in this step
         const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
@@ -1003,15 +1057,10 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     const unsigned epoch = ds->epoch;
     // range vb.id: offsets, non-empty tile list, and the clean tiles'
     // records moved unchanged to their new offsets
-    const int t0 = vb.id << g.lgRe, t1 = min(t0 + g.Re, g.ntiles);
-    const int t = t0 + (int)threadIdx.x;
-    const bool in = t < t1;
-    const unsigned c = in ? b.tcnt[t] : 0;
-    const bool dirty = in && tile_dirty(b, (unsigned)t, epoch, all_dirty);
+    const bool dirty = in && (all_dirty || tdv == epoch);
     unsigned tot, totz;
     const unsigned ex = block_exscan_u(c, s_red, &tot);
     const unsigned exz = block_exscan_u(c != 0 ? 1u : 0u, s_red, &totz);
-    const unsigned base = b.part_off[vb.id], abase = b.part_aoff[vb.id];
     if (in) {
         b.tstart[nxt][t] = base + ex;
         if (c)
@@ -1022,7 +1071,7 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     s_pre[threadIdx.x] = ex;
     if (threadIdx.x == kBlock - 1)
         s_pre[kBlock] = ex + c;
-    s_old[threadIdx.x] = (in && !dirty) ? b.tstart[cur][t] : 0xffffffffu;
+    s_old[threadIdx.x] = (in && !dirty) ? tso : 0xffffffffu;
     if (threadIdx.x == 0)
         s_ndl = 0;
     __syncthreads();
@@ -1056,15 +1105,19 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
         // dirty tiles from the flat list, round-robin over all waves
         const unsigned nd = ds->ndirty;
         for (unsigned item = vb.id * (kBlock / 64) + wv; item < nd; item += vb.n * (kBlock / 64)) {
-            const unsigned tt = b.dlist[b.dflat[item]];
-            if (!b.tcnt[tt])
-                continue;
+            const unsigned tt = b.dflat[item];
+            // every load of the tile is issued before any is used
+            const unsigned ctt = b.tcnt[tt];
+            const unsigned pbase = b.part_off[tt >> g.lgRe];
+            const unsigned* slot = b.tslot + (size_t)tt * kSlotWords;
+            const unsigned hdr = slot[0], word = slot[1 + lane];
             const int r0 = (int)(tt >> g.lgRe) << g.lgRe;
             unsigned part = 0;  // offset: the range's base plus the counts before tt in the range
             for (int k = r0 + lane; k < (int)tt; k += 64)
                 part += b.tcnt[k];
-            unsigned o = b.part_off[tt >> g.lgRe] + wave_sum_u(part);
-            wave_write_tile(g, b.lab, tt, W[wv], b.tslot + (size_t)tt * kSlotWords, rec, o);
+            const unsigned o = pbase + wave_sum_u(part);
+            if (ctt)
+                wave_write_tile(g, b.lab, tt, W[wv], hdr, word, rec, o);
         }
         return;
     }
@@ -1084,7 +1137,8 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
         for (int k = r0 + lane; k < (int)tt; k += 64)
             part += b.tcnt[k];
         unsigned o = b.part_off[tt >> g.lgRe] + wave_sum_u(part);
-        wave_write_tile(g, b.lab, tt, W[wv], b.tslot + (size_t)tt * kSlotWords, rec, o);
+        const unsigned* slot = b.tslot + (size_t)tt * kSlotWords;
+        wave_write_tile(g, b.lab, tt, W[wv], slot[0], slot[1 + lane], rec, o);
     }
 }
 
