@@ -165,6 +165,16 @@ Geom make_geom(const sobrc_params* p)
     g.sob_lds = g.stage_cap * 12 + fixed;
     int sg = g.ntiles < 2 * kMaxGrid ? g.ntiles : 2 * kMaxGrid;  // mostly one tile per block
     g.sob_grid = (sg + 7) / 8 * 8;
+    // PS model: tile-staged L2 gradient when the tile's box (tile and R pixels
+    // on every side; fp32 intensity and label, 8 bytes per pixel) fits the LDS bound
+    g.ps_lds = 0;
+    if (g.model == SOBRC_PS && !g.psf) {
+        const long long rz = g.ndim == 3 ? g.R : 0;
+        const long long cells = ((1LL << g.tsx) + 2LL * g.R) * ((1LL << g.tsy) + 2LL * g.R) * ((1LL << g.tsz) + 2 * rz);
+        const long long bytes = cells * 8;
+        if (bytes <= kPsLdsMax)
+            g.ps_lds = (int)bytes;
+    }
     return g;
 }
 

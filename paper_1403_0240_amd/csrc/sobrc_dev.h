@@ -14,6 +14,7 @@ constexpr int kMaxT = 1024;        // support table entries: d^2 < T <= (E/2)^2 
 constexpr int kMaxLim = 81;        // (h+1)^2 for the largest brick halo (2D, h = 8)
 constexpr int kSmallM = 16;        // label counts up to this use per-block statistics partials
 constexpr int kMaxGrid = 2048;     // blocks of the particle and emission kernels
+constexpr int kPsLdsMax = 64 * 1024;  // LDS bound of the tile-staged PS L2 gradient
 
 // Largest axis offset h with h*h < T: the halo a Sobolev brick needs.
 // Bricks exist for 3D halos 1..4 (8^3 tiles) and 2D halos 1..8 (16^2 tiles).
@@ -102,6 +103,7 @@ struct Geom {
     int stage_cap;              // generic-path staging capacity
     int sob_lds;                // dynamic LDS bytes of the generic Sobolev kernel
     int sob_grid;               // blocks of the Sobolev kernels (multiple of 8)
+    int ps_lds;                 // PS model: LDS bytes of the tile-staged L2 gradient (0: per particle)
     int dlistm;                 // dirty tiles go through a flat list balanced over all waves (ge <= kMaxGrid)
     int topo;                   // ranked acceptance with topological control
     int psf;                    // deconvolving model (Gaussian PSF)

@@ -1269,6 +1269,116 @@ __global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* i
     l2diff_body<PSF>(g, b, img, cur, out, gated, VB{blockIdx.x, gridDim.x});
 }
 
+// PS model, tile-staged: one block per non-empty tile (the active-tile list,
+// XCD-contiguous runs) copies the tile's box -- the tile and R pixels on every
+// side, intensity and label of each pixel in one 8-byte entry -- into LDS
+// once, and each of the tile's particles takes its PS ball sums and its
+// face-neighbour counts from there.  Pixels outside the image carry the label
+// kNone, which no particle's labels equal, so a ball row is walked over its
+// whole half-width w (w^2 <= R^2 - dy^2 - dz^2) without per-pixel tests; the
+// pixels that count are added in the same order as in the per-particle path
+// above (the others add +0), so the sums are the same fp32 values.
+__device__ __forceinline__ int isqrt_floor(int v)  // v >= 0
+{
+    int w = (int)sqrtf((float)v);
+    while (w * w > v)
+        --w;
+    while ((w + 1) * (w + 1) <= v)
+        ++w;
+    return w;
+}
+
+__device__ __forceinline__ void l2diff_ps_tile_body(const Geom& g, const Bufs& b, const void* img, int cur,
+                                                    float* __restrict__ out, int gated, VB vb)
+{
+    extern __shared__ __align__(16) char lds[];
+    DevState* ds = b.ds;
+    if (gated && vb.id == 0 && threadIdx.x == 0) {
+        ds->go = 0;
+        ds->undo = 0;
+        ds->epoch = ds->epoch + 1;
+        ds->lmode = (ds->lmode & ~1u) | (ds->switch_it != 0 ? 1u : 0u);
+    }
+    if (gated && stopped(ds))
+        return;
+    const int R = g.R, rz = g.ndim == 3 ? R : 0;
+    const int TX = 1 << g.tsx, TY = 1 << g.tsy, TZ = 1 << g.tsz;
+    const int BX = TX + 2 * R, BY = TY + 2 * R, BZ = TZ + 2 * rz, BXY = BX * BY;
+    const int nbox = BX * BY * BZ;
+    uint2* s_e = (uint2*)lds;  // (intensity bits, label)
+    unsigned a0, a1;
+    xcd_chunk(ds->n_active[cur], vb, a0, a1);
+    const unsigned* ts = b.tstart[cur];
+    const uint2* rec = b.rec[cur];
+    for (unsigned ai = a0; ai < a1; ++ai) {
+        const unsigned t = b.active[cur][ai];
+        const int tx = (int)(t % (unsigned)g.ntx), ty = (int)((t / (unsigned)g.ntx) % (unsigned)g.nty);
+        const int tz = (int)(t / ((unsigned)g.ntx * (unsigned)g.nty));
+        const int ox = tx * TX - R, oy = ty * TY - R, oz = tz * TZ - rz;
+        const unsigned p0 = ts[t], p1 = ts[t + 1];
+        __syncthreads();  // the previous tile is done with LDS
+        for (int k = threadIdx.x; k < nbox; k += kBlock) {
+            const int bx = k % BX, by = (k / BX) % BY, bz = k / BXY;
+            const int x = ox + bx, y = oy + by, z = oz + bz;
+            const bool in = x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+            const long long j = in ? lin_of(g, x, y, z) : 0;
+            s_e[k] = make_uint2(__float_as_uint(in ? img_at(g, img, j) : 0.f), in ? (unsigned)b.lab[j] : (unsigned)kNone);
+        }
+        __syncthreads();
+        for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
+            const uint2 r = rec[p];
+            int x, y, z;
+            unpack(g, r.x, x, y, z);
+            const unsigned a = r.y & 0xffffu, bl = r.y >> 16;
+            const int c = (x - ox) + BX * ((y - oy) + BY * (z - oz));
+            const float v = __uint_as_float(s_e[c].x);
+            int ca = 0, cb = 0;
+#define SOBRC_FACE(cond, j)                    \
+    if (cond) {                                \
+        const unsigned l = s_e[j].y;           \
+        ca += l == a;                          \
+        cb += l == bl;                         \
+    }
+            SOBRC_FACE(x > 0, c - 1)
+            SOBRC_FACE(x + 1 < g.nx, c + 1)
+            SOBRC_FACE(y > 0, c - BX)
+            SOBRC_FACE(y + 1 < g.ny, c + BX)
+            SOBRC_FACE(z > 0, c - BXY)
+            SOBRC_FACE(z + 1 < g.nz, c + BXY)
+#undef SOBRC_FACE
+            float sa = 0.f, sb = 0.f;
+            int na = 0, nb = 0;
+            for (int dz = -rz; dz <= rz; ++dz)
+                for (int dy = -R; dy <= R; ++dy) {
+                    const int rem = g.R2 - dy * dy - dz * dz;
+                    if (rem < 0)
+                        continue;
+                    const int w = isqrt_floor(rem);
+                    const uint2* row = s_e + c + BX * (dy + BY * dz);
+#pragma unroll 4
+                    for (int dx = -w; dx <= w; ++dx) {
+                        const uint2 e = row[dx];
+                        const float val = __uint_as_float(e.x);
+                        const bool ia = e.y == a, ib = e.y == bl;
+                        sa += ia ? val : 0.f;
+                        na += ia ? 1 : 0;
+                        sb += ib ? val : 0.f;
+                        nb += ib ? 1 : 0;
+                    }
+                }
+            const float ma = sa / (float)na, mb = sb / (float)nb;
+            const float dext = g.noise ? poisson_move(v, ma, mb) : (v - mb) * (v - mb) - (v - ma) * (v - ma);
+            out[p] = dext + g.lambda * (float)(ca - cb);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_l2diff_ps(Geom g, Bufs b, const void* img, int cur,
+                                                     float* __restrict__ out, int gated)
+{
+    l2diff_ps_tile_body(g, b, img, cur, out, gated, VB{blockIdx.x, gridDim.x});
+}
+
 // ------------------------------------------------- Sobolev update, Eq. (6)
 //
 // One block per non-empty tile (the cell of the cell list); blocks are mapped
@@ -2454,6 +2564,8 @@ hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur,
 {
     if (g.psf)
         hipLaunchKernelGGL(k_l2diff<true>, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, out, gated);
+    else if (g.ps_lds)
+        hipLaunchKernelGGL(k_l2diff_ps, dim3(g.sob_grid), dim3(kBlock), g.ps_lds, s, g, b, img, cur, out, gated);
     else
         hipLaunchKernelGGL(k_l2diff<false>, dim3(g.gp), dim3(kBlock), 0, s, g, b, img, cur, out, gated);
     return hipGetLastError();

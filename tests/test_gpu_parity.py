@@ -100,6 +100,13 @@ CASES = {
                                                      lam=0.7, noise=W.POISSON),
     "rand2d_poisson_ps": lambda: W.random_multilabel(23, (30, 34), 3, E=8.0, lam=0.5, model=W.PS,
                                                      ps_radius=3, noise=W.POISSON),
+    # PS balls of larger radius over several tiles with ragged edges: the
+    # tile-staged path (2D R = 8, 3D R = 4) and, with a 3D box beyond its LDS
+    # bound (R = 7), the per-particle path
+    "ps2d_r8": lambda: W.random_multilabel(31, (70, 53), 3, E=8.0, lam=0.3, model=W.PS, ps_radius=8),
+    "ps3d_r4_u16": lambda: W.random_multilabel(32, (21, 18, 19), 2, dtype=np.uint16, E=6.0, lam=2e4,
+                                               model=W.PS, ps_radius=4),
+    "ps3d_r7": lambda: W.random_multilabel(33, (17, 16, 18), 2, E=6.0, lam=0.2, model=W.PS, ps_radius=7),
 }
 
 
