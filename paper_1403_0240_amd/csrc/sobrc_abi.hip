@@ -171,7 +171,7 @@ Geom make_geom(const sobrc_params* p)
     if (g.model == SOBRC_PS && !g.psf) {
         const long long rz = g.ndim == 3 ? g.R : 0;
         const long long cells = ((1LL << g.tsx) + 2LL * g.R) * ((1LL << g.tsy) + 2LL * g.R) * ((1LL << g.tsz) + 2 * rz);
-        const long long bytes = cells * 8;
+        const long long bytes = cells * 8 + (2LL * g.R + 1) * (2 * rz + 1) * 4;  // box, row half-widths
         if (bytes <= kPsLdsMax)
             g.ps_lds = (int)bytes;
     }

@@ -1277,7 +1277,8 @@ __global__ __launch_bounds__(kBlock) void k_l2diff(Geom g, Bufs b, const void* i
 // kNone, which no particle's labels equal, so a ball row is walked over its
 // whole half-width w (w^2 <= R^2 - dy^2 - dz^2) without per-pixel tests; the
 // pixels that count are added in the same order as in the per-particle path
-// above (the others add +0), so the sums are the same fp32 values.
+// above (the others add +0), so the sums are the same fp32 values.  The row
+// half-widths are tabulated once per block.
 __device__ __forceinline__ int isqrt_floor(int v)  // v >= 0
 {
     int w = (int)sqrtf((float)v);
@@ -1306,6 +1307,13 @@ __device__ __forceinline__ void l2diff_ps_tile_body(const Geom& g, const Bufs& b
     const int BX = TX + 2 * R, BY = TY + 2 * R, BZ = TZ + 2 * rz, BXY = BX * BY;
     const int nbox = BX * BY * BZ;
     uint2* s_e = (uint2*)lds;  // (intensity bits, label)
+    int* s_w = (int*)(s_e + nbox);  // half-width of ball row (dy, dz), -1 if empty
+    const int nrow = (2 * R + 1) * (2 * rz + 1);
+    for (int k = threadIdx.x; k < nrow; k += kBlock) {
+        const int dy = k % (2 * R + 1) - R, dz = k / (2 * R + 1) - rz;
+        const int rem = g.R2 - dy * dy - dz * dz;
+        s_w[k] = rem < 0 ? -1 : isqrt_floor(rem);
+    }
     unsigned a0, a1;
     xcd_chunk(ds->n_active[cur], vb, a0, a1);
     const unsigned* ts = b.tstart[cur];
@@ -1350,10 +1358,9 @@ __device__ __forceinline__ void l2diff_ps_tile_body(const Geom& g, const Bufs& b
             int na = 0, nb = 0;
             for (int dz = -rz; dz <= rz; ++dz)
                 for (int dy = -R; dy <= R; ++dy) {
-                    const int rem = g.R2 - dy * dy - dz * dz;
-                    if (rem < 0)
+                    const int w = s_w[(dy + R) + (2 * R + 1) * (dz + rz)];
+                    if (w < 0)
                         continue;
-                    const int w = isqrt_floor(rem);
                     const uint2* row = s_e + c + BX * (dy + BY * dz);
 #pragma unroll 4
                     for (int dx = -w; dx <= w; ++dx) {
