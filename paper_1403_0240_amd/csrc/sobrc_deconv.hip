@@ -59,14 +59,23 @@ __global__ __launch_bounds__(kBlock) void k_psf_pass_x(Geom g, Bufs b, Psf k, co
 }
 
 // axis 1 (y) or 2 (z): blockIdx.x: 64 columns of x, blockIdx.y: kPsfSeg
-// positions along the axis, blockIdx.z: the remaining coordinate.
+// positions along the axis, blockIdx.z: the remaining coordinate.  Each thread
+// issues all of its staging loads before storing any, then computes four
+// consecutive outputs o0 .. o0 + 3 of its column tap by tap: at tap t a window
+// of registers holds s[o0 + t .. o0 + t + 3], one new value is read from LDS
+// per tap, and each output still adds its taps in order 0 .. 2r.
 __global__ __launch_bounds__(kBlock) void k_psf_pass_yz(Geom g, Bufs b, Psf k, const float* __restrict__ src,
                                                        int lab_i, float* __restrict__ dst, int axis, int squared)
 {
-    __shared__ float s[kPsfSeg + 2 * kPsfMaxR][64];
+    constexpr int kRows = kPsfSeg + 2 * kPsfMaxR;
+    constexpr int kGroups = kBlock / 64;               // row groups
+    constexpr int kPer = (kRows + kGroups - 1) / kGroups;  // staged rows per thread
+    constexpr int kOut = kPsfSeg / kGroups;             // consecutive outputs per thread
+    static_assert(kPsfSeg % kGroups == 0, "outputs per thread");
+    __shared__ float s[kRows][64];
     if (stopped_dc(b.ds))
         return;
-    const int lx = threadIdx.x & 63, lr = threadIdx.x >> 6;  // column, row group (4)
+    const int lx = threadIdx.x & 63, lr = threadIdx.x >> 6;  // column, row group
     const int x = blockIdx.x * 64 + lx;
     const int a0 = blockIdx.y * kPsfSeg;
     const int n_axis = axis == 1 ? g.ny : g.nz;
@@ -74,22 +83,43 @@ __global__ __launch_bounds__(kBlock) void k_psf_pass_yz(Geom g, Bufs b, Psf k, c
     // base index of (x, a = 0, other coordinate)
     const long long base = axis == 1 ? (long long)g.nx * g.ny * blockIdx.z + x : (long long)g.nx * blockIdx.z + x;
     const int n = kPsfSeg + 2 * k.r;
-    for (int j = lr; j < n; j += kBlock / 64) {
+    float v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int j = lr + kGroups * q;
         const int a = a0 - k.r + j;
-        s[j][lx] = (x < g.nx && a >= 0 && a < n_axis) ? psf_src(b, src, lab_i, base + a * stride) : 0.f;
+        v[q] = (j < n && x < g.nx && a >= 0 && a < n_axis) ? psf_src(b, src, lab_i, base + a * stride) : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int j = lr + kGroups * q;
+        if (j < n)
+            s[j][lx] = v[q];
     }
     __syncthreads();
     if (x >= g.nx)
         return;
     const float* taps = squared ? k.k2 : k.k;
-    for (int o = lr; o < kPsfSeg; o += kBlock / 64) {
-        const int a = a0 + o;
-        if (a >= n_axis)
-            break;
-        float acc = 0.f;
-        for (int t = 0; t <= 2 * k.r; ++t)
-            acc += taps[t] * s[o + t][lx];
-        dst[base + a * stride] = acc;
+    static_assert(kOut == 4, "a window of four outputs");
+    const int o0 = kOut * lr, T = 2 * k.r;
+    float acc[kOut] = {0.f, 0.f, 0.f, 0.f};
+    float w0 = s[o0][lx], w1 = s[o0 + 1][lx], w2 = s[o0 + 2][lx];
+    for (int t = 0; t <= T; ++t) {
+        const float w3 = s[o0 + t + 3][lx];  // o0 + T + 3 <= kPsfSeg - 1 + T < n
+        const float c = taps[t];
+        acc[0] += c * w0;
+        acc[1] += c * w1;
+        acc[2] += c * w2;
+        acc[3] += c * w3;
+        w0 = w1;
+        w1 = w2;
+        w2 = w3;
+    }
+#pragma unroll
+    for (int j = 0; j < kOut; ++j) {
+        const int a = a0 + o0 + j;
+        if (a < n_axis)
+            dst[base + a * stride] = acc[j];
     }
 }
 
