@@ -107,6 +107,10 @@ CASES = {
     "ps3d_r4_u16": lambda: W.random_multilabel(32, (21, 18, 19), 2, dtype=np.uint16, E=6.0, lam=2e4,
                                                model=W.PS, ps_radius=4),
     "ps3d_r7": lambda: W.random_multilabel(33, (17, 16, 18), 2, E=6.0, lam=0.2, model=W.PS, ps_radius=7),
+    # PS with per-pixel random labels: up to three records per pixel, so a
+    # tile holds more particles than a block has threads
+    "ps2d_noise4": lambda: W.random_multilabel(34, (23, 29), 4, blobs=False, E=8.0, lam=0.3, model=W.PS,
+                                               ps_radius=3),
 }
 
 
