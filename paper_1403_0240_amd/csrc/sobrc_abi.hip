@@ -384,6 +384,7 @@ struct sobrc_batch {
     unsigned* d_par = nullptr;
     unsigned* d_off = nullptr;
     uint4* d_state = nullptr;    // gathered per-slot state words
+    unsigned* d_tpre = nullptr;  // prefix of the slots' non-empty tile counts
     std::vector<sobrc_ctx*> slot;
     std::vector<unsigned> off;   // host copy, kNumPh rows of nslot + 1
     unsigned totals[kNumPh] = {};
@@ -869,7 +870,7 @@ int32_t get_gradient_mode(sobrc_ctx* c, int32_t* h_switch_iter, void* stream)
 namespace {
 
 struct BLayout {
-    size_t desc, par, off, state, total;
+    size_t desc, par, off, state, tpre, total;
 };
 
 BLayout batch_layout(int nslot)
@@ -885,6 +886,7 @@ BLayout batch_layout(int nslot)
     L.par = take(4 * (size_t)nslot);
     L.off = take(4 * (size_t)kNumPh * (size_t)(nslot + 1));
     L.state = take(16 * (size_t)nslot);
+    L.tpre = take(4 * (size_t)(nslot + 1));
     L.total = o;
     return L;
 }
@@ -938,6 +940,7 @@ void batch_offsets(sobrc_batch* B)
                 items = ph == kPhPart ? (unsigned)g.gp
                         : ph == kPhEmit ? (unsigned)g.ge
                         : ph == kPhSob  ? (unsigned)g.sob_grid
+                        : ph == kPhList ? (g.dlistm ? (unsigned)std::min(g.ge, kBatchListItems) : 0u)
                                         : 1u;
             }
             unsigned end = o[i] + items;
@@ -958,7 +961,7 @@ void batch_drop_graphs(sobrc_batch* B)
 
 int32_t batch_launch(sobrc_batch* B, int mode, float tol, hipStream_t s)
 {
-    BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+    BatchTab t{B->d_desc, B->d_par, B->d_off, B->d_tpre, B->nslot};
     const int l2 = mode == SOBRC_MODE_L2;
     const int flags = kGate | (mode == SOBRC_MODE_AUTO ? kAuto : 0);
     SOBRC_HIP(launch_batch_step(t, B->totals, B->g0, B->sw, l2, flags, tol, s), "batched step");
@@ -972,7 +975,7 @@ int32_t batch_states(sobrc_batch* B, std::vector<uint4>& st, hipStream_t s)
     st.assign((size_t)B->nslot, make_uint4(0u, 0u, 0u, 0u));
     if (!B->has_class)
         return SOBRC_OK;
-    BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+    BatchTab t{B->d_desc, B->d_par, B->d_off, B->d_tpre, B->nslot};
     SOBRC_HIP(launch_batch_gather(t, B->d_state, s), "kb_gather");
     SOBRC_HIP(hipMemcpyAsync(st.data(), B->d_state, st.size() * sizeof(uint4), hipMemcpyDeviceToHost, s),
               "hipMemcpyAsync");
@@ -994,7 +997,7 @@ int32_t batch_enqueue(sobrc_batch* B, int32_t iters, float tol, int32_t mode, hi
 {
     if (!B->has_class || iters <= 0)
         return SOBRC_OK;
-    BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+    BatchTab t{B->d_desc, B->d_par, B->d_off, B->d_tpre, B->nslot};
     SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
     int k = 0;
     if (iters >= 2) {
@@ -1068,6 +1071,7 @@ int32_t batch_create(int32_t n_slots, void* d_workspace, size_t bytes, sobrc_bat
     B->d_par = (unsigned*)(B->ws + L.par);
     B->d_off = (unsigned*)(B->ws + L.off);
     B->d_state = (uint4*)(B->ws + L.state);
+    B->d_tpre = (unsigned*)(B->ws + L.tpre);
     B->slot.assign((size_t)n_slots, nullptr);
     batch_offsets(B);
     std::vector<ImgDesc> empty((size_t)n_slots);
@@ -1201,7 +1205,7 @@ int32_t batch_collect(sobrc_batch* B, int32_t* h_iters, int32_t* h_stopped, void
             status = slot_status(st[i]);
     }
     if (B->has_class) {
-        BatchTab t{B->d_desc, B->d_par, B->d_off, B->nslot};
+        BatchTab t{B->d_desc, B->d_par, B->d_off, B->d_tpre, B->nslot};
         SOBRC_HIP(launch_batch_clear(t, s), "kb_clear");
     }
     return status;

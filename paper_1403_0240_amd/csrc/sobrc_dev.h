@@ -200,7 +200,11 @@ struct ImgDesc {
 // launch on its own -- particle kernels (gp), emission kernels (ge), the
 // Sobolev kernel (sob_grid), one scan block.  Each slot's range starts at a
 // multiple of 8 so that item & 7 names the XCD as in a stand-alone launch.
-enum { kPhPart = 0, kPhEmit = 1, kPhSob = 2, kPhScan = 3, kNumPh = 4 };
+enum { kPhPart = 0, kPhEmit = 1, kPhSob = 2, kPhScan = 3, kPhList = 4, kNumPh = 5 };
+// blocks of the batched dirty-tile count per image (its waves take the
+// image's dirty tiles round-robin; each block forms the prefix of the
+// image's list lengths, so more blocks than the dirty tiles need only cost)
+constexpr int kBatchListItems = 32;
 constexpr int kPersist = 2048;  // blocks of a persistent batched launch
 constexpr int kListGrid = 1024;  // blocks of the dirty-list count (all resident at once)
 
@@ -208,6 +212,7 @@ struct BatchTab {
     const ImgDesc* d;     // nslot descriptors
     unsigned* par;        // per slot: parity of the current state buffer
     const unsigned* off;  // kNumPh rows of nslot + 1 item offsets
+    unsigned* tpre;       // nslot + 1: prefix of the slots' non-empty tile counts (device-written)
     int nslot;
 };
 

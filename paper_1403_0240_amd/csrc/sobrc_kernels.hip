@@ -693,9 +693,10 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     static_assert(kMaxGrid == 8 * kBlock, "eight list lengths per thread");
     const int ge = g.ge;
     const int i0 = (int)threadIdx.x * 8;
-    const uint4* dc = (const uint4*)b.dcnt;  // kMaxGrid entries; those >= ge are ignored
+    const uint4* dc = (const uint4*)b.dcnt;  // kMaxGrid entries; only those < ge are read
     // the list lengths are loaded with the stop flag (in bounds either way)
-    const uint4 q0 = dc[2 * threadIdx.x], q1 = dc[2 * threadIdx.x + 1];
+    const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+    const uint4 q0 = i0 < ge ? dc[2 * threadIdx.x] : z4, q1 = i0 + 4 < ge ? dc[2 * threadIdx.x + 1] : z4;
     if (gated && stopped(b.ds))
         return;
     unsigned c[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
@@ -1609,8 +1610,13 @@ constexpr TapList<BrickShape<ND, H>::NT> make_taps()
     return t;
 }
 
+// Tiles active[cur][a0 .. a1) of one context through the brick kernel (the
+// tile loop stays inside this function: the compiler keeps its registers
+// lean that way).
 template <int ND, int H, bool FULL>
-__device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* __restrict__ in, float* __restrict__ out, int gated, VB vb)
+__device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const SobW& sw, int cur,
+                                            const float* __restrict__ in, float* __restrict__ out, int gated,
+                                            unsigned a0, unsigned a1)
 {
     using S = BrickShape<ND, H>;
     constexpr TapList<S::NT> taps = make_taps<ND, H>();
@@ -1636,8 +1642,6 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
         return;
     if ((gated & kAuto) && (ds->lmode & 1u))
         return;  // L2 gradients in force: no smoothing
-    unsigned a0, a1;
-    xcd_chunk(ds->n_active[cur], vb, a0, a1);
     const unsigned* ts = b.tstart[cur];
     const int lane = lane_id();
     for (unsigned ai = a0; ai < a1; ++ai) {
@@ -1823,6 +1827,14 @@ __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b,
             out[cs + e] = res;
         }
     }
+}
+
+template <int ND, int H, bool FULL>
+__device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* __restrict__ in, float* __restrict__ out, int gated, VB vb)
+{
+    unsigned a0, a1;
+    xcd_chunk(b.ds->n_active[cur], vb, a0, a1);
+    brick_range<ND, H, FULL>(g, b, sw, cur, in, out, gated, a0, a1);
 }
 
 template <int ND, int H, bool FULL>
@@ -2730,8 +2742,26 @@ __device__ __forceinline__ int slot_of(const unsigned* __restrict__ off, int nsl
 }
 
 __global__ __launch_bounds__(kBlock) void kb_l2diff(const ImgDesc* __restrict__ d, const unsigned* __restrict__ par,
-                                                   const unsigned* __restrict__ offs, int nslot)
+                                                   const unsigned* __restrict__ offs, int nslot,
+                                                   unsigned* __restrict__ tpre)
 {
+    if (blockIdx.x == 0) {
+        // prefix of the slots' non-empty tile counts (state par[i]) for the
+        // batched Sobolev kernel, which deals the batch's tiles to its blocks
+        __shared__ unsigned s_red[kBlock / 64];
+        unsigned carry = 0;
+        for (int i0 = 0; i0 < nslot; i0 += kBlock) {
+            const int i = i0 + (int)threadIdx.x;
+            const unsigned n = (i < nslot && d[i].live) ? d[i].b.ds->n_active[par[i]] : 0u;
+            unsigned tot;
+            const unsigned ex = block_exscan_u(n, s_red, &tot);
+            if (i < nslot)
+                tpre[i] = carry + ex;
+            carry += tot;
+        }
+        if (threadIdx.x == 0)
+            tpre[nslot] = carry;
+    }
     const unsigned* off = offs + kPhPart * (nslot + 1);
     const unsigned total = off[nslot];
     for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
@@ -2761,21 +2791,24 @@ __global__ __launch_bounds__(kSobBlock) void kb_sobolev_generic(const ImgDesc* _
 }
 
 template <int ND, int H, bool FULL>
+// The batch's non-empty tiles, numbered through all slots (tpre: the prefix
+// of their counts, written by kb_l2diff), are dealt to the blocks in
+// contiguous runs (XCD-contiguous as in a stand-alone launch): the blocks
+// follow the tiles that hold particles in this iteration instead of a fixed
+// share of every image's tiles.
 __global__ __launch_bounds__(kSobBlock) void kb_sobolev_brick(const ImgDesc* __restrict__ d,
                                                              const unsigned* __restrict__ par,
-                                                             const unsigned* __restrict__ offs, int nslot, SobW sw,
+                                                             const unsigned* __restrict__ tpre, int nslot, SobW sw,
                                                              int gated)
 {
-    const unsigned* off = offs + kPhSob * (nslot + 1);
-    const unsigned total = off[nslot];
-    for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
-        const int i = slot_of(off, nslot, item);
+    unsigned a0, a1;
+    xcd_chunk(tpre[nslot], VB{blockIdx.x, gridDim.x}, a0, a1);
+    for (unsigned k = a0; k < a1;) {
+        const int i = slot_of(tpre, nslot, k);  // slot whose run holds tile k (never an empty one)
+        const unsigned e = min(a1, tpre[i + 1]);
         const ImgDesc& D = d[i];
-        const unsigned v = item - off[i];
-        if (v < (unsigned)D.g.sob_grid)
-            sobolev_brick_body<ND, H, FULL>(D.g, D.b, sw, (int)par[i], D.b.dE, D.b.gH1, gated,
-                                            VB{v, (unsigned)D.g.sob_grid});
-        __syncthreads();
+        brick_range<ND, H, FULL>(D.g, D.b, sw, (int)par[i], D.b.dE, D.b.gH1, gated, k - tpre[i], e - tpre[i]);
+        k = e;
     }
 }
 
@@ -2815,14 +2848,15 @@ template <int ND>
 __global__ __launch_bounds__(kBlock) void kb_count_list(const ImgDesc* __restrict__ d,
                                                        const unsigned* __restrict__ offs, int nslot)
 {
-    const unsigned* off = offs + kPhEmit * (nslot + 1);
+    const unsigned* off = offs + kPhList * (nslot + 1);
     const unsigned total = off[nslot];
     for (unsigned item = blockIdx.x; item < total; item += gridDim.x) {
         const int i = slot_of(off, nslot, item);
         const ImgDesc& D = d[i];
         const unsigned v = item - off[i];
-        if (v < (unsigned)D.g.ge && D.g.dlistm)
-            count_list_body<ND>(D.g, D.b, 1, VB{v, (unsigned)D.g.ge});
+        const unsigned nb = (unsigned)min(D.g.ge, kBatchListItems);
+        if (v < nb && D.g.dlistm)
+            count_list_body<ND>(D.g, D.b, 1, VB{v, nb});
         __syncthreads();
     }
 }
@@ -2905,7 +2939,8 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
                              int flags, float tol, hipStream_t s)
 {
     const int ns = t.nslot;
-    hipLaunchKernelGGL(kb_l2diff, persistent_grid(totals[kPhPart]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns);
+    hipLaunchKernelGGL(kb_l2diff, persistent_grid(totals[kPhPart]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns,
+                       t.tpre);
     if (!l2) {
         const dim3 gd = persistent_grid(totals[kPhSob]);
         bool done = false;
@@ -2913,11 +2948,11 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
 #define SOBRC_BRICK(ND, H)                                                                                   \
     if (!done && g0.ndim == ND && g0.h == H) {                                                                \
         if (g0.full)                                                                                          \
-            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, true>), gd, dim3(kSobBlock), 0, s, t.d, t.par, t.off, \
-                               ns, sw, flags);                                                                \
+            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, true>), dim3(kPersist), dim3(kSobBlock), 0, s, t.d,  \
+                               t.par, t.tpre, ns, sw, flags);                                                 \
         else                                                                                                  \
-            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, false>), gd, dim3(kSobBlock), 0, s, t.d, t.par,       \
-                               t.off, ns, sw, flags);                                                         \
+            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, false>), dim3(kPersist), dim3(kSobBlock), 0, s, t.d, \
+                               t.par, t.tpre, ns, sw, flags);                                                 \
         done = true;                                                                                          \
     }
             SOBRC_BRICK(3, 1) SOBRC_BRICK(3, 2) SOBRC_BRICK(3, 3) SOBRC_BRICK(3, 4)
@@ -2935,11 +2970,11 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
     if (g0.ndim == 3) {
         hipLaunchKernelGGL(kb_count<3>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off,
                            ns);
-        hipLaunchKernelGGL(kb_count_list<3>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.off, ns);
+        hipLaunchKernelGGL(kb_count_list<3>, persistent_grid(totals[kPhList]), dim3(kBlock), 0, s, t.d, t.off, ns);
     } else {
         hipLaunchKernelGGL(kb_count<2>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off,
                            ns);
-        hipLaunchKernelGGL(kb_count_list<2>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.off, ns);
+        hipLaunchKernelGGL(kb_count_list<2>, persistent_grid(totals[kPhList]), dim3(kBlock), 0, s, t.d, t.off, ns);
     }
     hipLaunchKernelGGL(kb_scan, dim3(nsc), dim3(kScanThreads), 0, s, t.d, t.par, t.off, ns, tol, flags);
     hipLaunchKernelGGL(kb_write, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
