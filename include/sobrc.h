@@ -270,8 +270,10 @@ int32_t batch_collect(sobrc_batch* batch, int32_t* h_iters, int32_t* h_stopped, 
 
 /* Launch shape of the batch's slots: particles per block-item of the
  * particle kernels (part_chunk), log2 of the tiles per emission range
- * (lg_range, <= 8) and tiles per Sobolev block-item (sob_tiles); 0 keeps each
- * context's own stand-alone value.  Shapes only regroup the work -- integer
+ * (lg_range, <= 8) and tiles per Sobolev block-item of the generic Sobolev
+ * kernel (sob_tiles; the brick kernel takes the batch's non-empty tiles as
+ * they come); 0 keeps each context's own stand-alone value.  Shapes only
+ * regroup the work -- integer
  * partial sums, the tile-major particle order and every tile's Sobolev sums
  * are unchanged -- so results do not depend on them.  Synchronises. */
 int32_t batch_set_shape(sobrc_batch* batch, int32_t part_chunk, int32_t lg_range,

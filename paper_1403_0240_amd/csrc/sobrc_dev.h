@@ -198,8 +198,11 @@ struct ImgDesc {
 
 // Item spaces of a batched step: per slot, the blocks the context would
 // launch on its own -- particle kernels (gp), emission kernels (ge), the
-// Sobolev kernel (sob_grid), one scan block.  Each slot's range starts at a
+// generic Sobolev kernel (sob_grid), one scan block -- and the blocks of the
+// dirty-tile count (at most kBatchListItems).  Each slot's range starts at a
 // multiple of 8 so that item & 7 names the XCD as in a stand-alone launch.
+// The brick Sobolev kernel instead deals the batch's non-empty tiles
+// (BatchTab::tpre).
 enum { kPhPart = 0, kPhEmit = 1, kPhSob = 2, kPhScan = 3, kPhList = 4, kNumPh = 5 };
 // blocks of the batched dirty-tile count per image (its waves take the
 // image's dirty tiles round-robin; each block forms the prefix of the
