@@ -111,6 +111,10 @@ CASES = {
     # tile holds more particles than a block has threads
     "ps2d_noise4": lambda: W.random_multilabel(34, (23, 29), 4, blobs=False, E=8.0, lam=0.3, model=W.PS,
                                                ps_radius=3),
+    # the largest tile-staged boxes: 3D R = 6 (64000 bytes of box) and the
+    # largest radius, 2D R = 32 (a ball wider than the image)
+    "ps3d_r6": lambda: W.random_multilabel(35, (14, 15, 13), 2, E=6.0, lam=0.2, model=W.PS, ps_radius=6),
+    "ps2d_r32": lambda: W.random_multilabel(36, (40, 45), 2, E=8.0, lam=0.3, model=W.PS, ps_radius=32),
 }
 
 
