@@ -115,7 +115,15 @@ CASES = {
     # largest radius, 2D R = 32 (a ball wider than the image)
     "ps3d_r6": lambda: W.random_multilabel(35, (14, 15, 13), 2, E=6.0, lam=0.2, model=W.PS, ps_radius=6),
     "ps2d_r32": lambda: W.random_multilabel(36, (40, 45), 2, E=8.0, lam=0.3, model=W.PS, ps_radius=32),
+    # more labels than the per-block statistics partials hold (16): region
+    # sums by atomics in the acceptance kernel
+    "many_labels_2d": lambda: W.random_multilabel(40, (48, 52), 24, E=8.0, lam=0.3),
+    "many_labels_3d": lambda: W.random_multilabel(41, (14, 16, 15), 20, E=6.0, lam=0.3),
+    "many_labels_3d_u16": lambda: W.random_multilabel(42, (15, 13, 16), 40, dtype=np.uint16, E=6.0, lam=2e4),
 }
+# particle capacity where the default (a quarter of the pixels, at least 4096)
+# is too small for the case's contours
+CAPS = {"many_labels_3d": 16384, "many_labels_3d_u16": 16384}
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
@@ -123,7 +131,7 @@ def test_particles_and_gradients(ora, name):
     w = CASES[name]()
     print(f"[case {name} shape={w.image.shape}]", flush=True)
     P = ora.params_of(w)
-    ctx, img, lab = gpu_state(w)
+    ctx, img, lab = gpu_state(w, cap=CAPS.get(name))
     lin_o, a_o, b_o = ora.particles(P, w.labels)
     perm, lin, a, b = match_order(ctx, lin_o, b_o)
     assert np.array_equal(a[perm], a_o)
@@ -156,7 +164,7 @@ def test_step_trajectory(ora, name):
     w = CASES[name]()
     print(f"[case {name} shape={w.image.shape}]", flush=True)
     P = ora.params_of(w)
-    ctx, img, lab = gpu_state(w)
+    ctx, img, lab = gpu_state(w, cap=CAPS.get(name))
     L_o = w.labels.copy()
     nfl = torch.zeros(1, dtype=torch.int32, device="cuda")
     steps = 12
