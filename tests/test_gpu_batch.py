@@ -184,11 +184,13 @@ def test_launch_shapes_do_not_change_results(dims):
 
 
 def test_batch_mixes_likelihoods():
-    """Slots with Poisson noise and the piecewise-smooth model run in the same
-    batch as Gaussian piecewise-constant slots, each equal to its own run."""
+    """Slots with Poisson noise, the piecewise-smooth model or more than 16
+    labels (region sums by atomics) run in the same batch as Gaussian
+    piecewise-constant slots, each equal to its own run."""
     ws = [W.random_multilabel(22, (30, 34), 3, E=6.0, lam=0.5, model=W.PS, ps_radius=3, noise=W.POISSON),
           W.random_multilabel(23, (27, 41), 3, E=6.0, lam=0.7, noise=W.POISSON),
-          W.blobs2d(210, side_lo=40, side_hi=120, E=6.0)]
+          W.blobs2d(210, side_lo=40, side_hi=120, E=6.0),
+          W.random_multilabel(43, (44, 50), 24, E=6.0, lam=0.3)]
     print(f"[batch likelihood mix n={len(ws)}]", flush=True)
     iters = 7
     solo = []
