@@ -120,6 +120,11 @@ CASES = {
     "many_labels_2d": lambda: W.random_multilabel(40, (48, 52), 24, E=8.0, lam=0.3),
     "many_labels_3d": lambda: W.random_multilabel(41, (14, 16, 15), 20, E=6.0, lam=0.3),
     "many_labels_3d_u16": lambda: W.random_multilabel(42, (15, 13, 16), 40, dtype=np.uint16, E=6.0, lam=2e4),
+    # degenerate extents: volumes one or two voxels thick, images one pixel wide
+    "thin3d_nz1": lambda: W.random_multilabel(44, (1, 40, 37), 3, E=6.0, lam=0.3),
+    "thin3d_nz2": lambda: W.random_multilabel(45, (2, 30, 33), 3, E=6.0, lam=0.3),
+    "row2d_ny1": lambda: W.random_multilabel(46, (1, 70), 3, E=6.0, lam=0.3),
+    "col2d_nx1": lambda: W.random_multilabel(47, (50, 1), 3, E=6.0, lam=0.3),
 }
 # particle capacity where the default (a quarter of the pixels, at least 4096)
 # is too small for the case's contours
