@@ -163,6 +163,9 @@ RUNS = {
     "blobs3d": lambda: W.random_multilabel(42, (17, 19, 18), 3, E=6.0, lam=0.4),
     "u16_3d": lambda: W.random_multilabel(43, (14, 20, 12), 3, dtype=np.uint16, E=6.0, lam=30.0),
     "disk2d_128": lambda: W.disk2d(),
+    # the acceptance with the PS model and with more than 16 labels
+    "ps2d": lambda: W.random_multilabel(48, (40, 44), 3, E=6.0, lam=0.3, model=W.PS, ps_radius=3),
+    "many_labels_2d": lambda: W.random_multilabel(49, (44, 50), 24, E=6.0, lam=0.3),
 }
 
 
