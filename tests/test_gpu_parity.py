@@ -398,7 +398,7 @@ def test_full_size_first_step(ora, name):
     print(f"  N={len(lin)} marginal label differences: {nd}")
 
 
-@pytest.mark.parametrize("name", ["disk2d_128", "rand3d_u16"])
+@pytest.mark.parametrize("name", ["disk2d_128", "rand3d_u16", "rand2d_ps", "many_labels_2d"])
 def test_auto_mode_matches_oracle(ora, name):
     """AUTO gradient mode: same per-iteration particle counts, flips and
     reversals as the oracle, the same switch to L2 gradients, the same stop
