@@ -33,14 +33,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# Algorithmic bytes per particle for each kernel (each input read once, each
-# output written once; neighbour data reused on chip is not counted).
+# Algorithmic bytes per particle that each kernel itself moves (each input
+# read once, each output written once; neighbour data reused on chip is not
+# counted).
 #   k_l2diff : record 8 + intensity 2 (u16) + face-label stencil 3.4 + gradient write 4
 #   k_sobolev: record 8 + L2 gradient read 4 + Sobolev gradient write 4
 #   k_flip   : record 8 + gradient read 4
 #   k_write  : record write 8 (the particle set of the next iteration)
-ALG_BYTES = {"k_l2diff": 17.4, "k_sobolev": 16.0, "k_flip": 12.0, "k_write": 8.0}
-
+KERNEL_OWN_BYTES = {"k_l2diff": 17.4, "k_sobolev": 16.0, "k_flip": 12.0, "k_write": 8.0}
 
 
 
@@ -103,6 +103,42 @@ def copy_probe():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}), flush=True)
+
+
+def copy_bandwidth():
+    """Measured HBM bandwidth of a plain 1 GiB device copy (read + write
+    bytes over the median of five copies timed with events on the current
+    stream): the practical ceiling beside the 8 TB/s peak."""
+    import torch
+    n = 256 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    t = float(np.median(times))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * 4 * n, "seconds": t, "gbs": 2 * 4 * n / t / 1e9}
+
+
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def batch_bench(a):
@@ -249,23 +285,35 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, budget_s):
-    """FP64 oracle iterations from the seeded start until the budget is spent."""
+def _oracle_rate(w, threads, budget_s, max_iters):
     from oracle import oracle as O
-    threads = min(os.cpu_count() or 1, 16)
     P = O.params_of(w, threads=threads)
     L = w.labels.copy()
     I = w.image.astype(np.float64)
     done, upd = 0, 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and done < w.iterations:
+    while done < min(max_iters, w.iterations) and (done == 0 or time.perf_counter() - t0 < budget_s):
         L, info = O.step(P, I, L, O.MODE_SOBOLEV, want_arrays=False)
         upd += info["n"]
         done += 1
-    dt = time.perf_counter() - t0
+    return upd, done, time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle on the host: iterations from the seeded start on all
+    host cores (at most 16 threads) until the budget is spent, and the first
+    iteration on one thread."""
+    threads = min(os.cpu_count() or 1, 16)
+    upd, done, dt = _oracle_rate(w, threads, budget_s, 1 << 30)
+    upd1, done1, dt1 = _oracle_rate(w, 1, 0.0, 1)
     return {"value": upd / dt, "unit": "particle-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {done} iterations of {w.name} from the seeded start "
-                      f"({upd} particle updates in {dt:.1f} s, FP64, OpenMP over particles)"}
+                      f"({upd} particle updates in {dt:.1f} s, FP64, OpenMP over particles, "
+                      f"{threads} threads)",
+            "one_thread": {"value": upd1 / dt1, "unit": "particle-updates/s", "cores": 1,
+                           "sample": f"first {done1} iteration(s) of {w.name} ({upd1} particle "
+                                     f"updates in {dt1:.1f} s)"},
+            "host": host_info()}
 
 
 def main():
@@ -357,26 +405,43 @@ def main():
         rec["kernels"] = kt
         rec["ms_per_step_with_events"] = dt_ev * 1e3 / a.steps
         dom = max(kt, key=lambda k: kt[k]["ms_total"])
-        per = ALG_BYTES.get(dom)
-        if per is not None and kt[dom]["ms_total"] > 0:
+        gb = grad_eval_bytes(w)
+        copy = copy_bandwidth()
+        rec["hbm_copy"] = copy
+        own = KERNEL_OWN_BYTES.get(dom)
+        if own is not None and kt[dom]["ms_total"] > 0:
+            # priced at the algorithmic bytes of one particle-update of the
+            # gradient evaluation (record, intensity, face labels, sorted
+            # record write, Sobolev gradient write); the kernel's own bytes
+            # beside it
             launches = kt[dom]["launches"]
-            alg_per_launch = per * updates / launches
-            achieved = alg_per_launch / (kt[dom]["us_avg"] * 1e-6) / 1e9
+            alg_per_launch = gb * updates / launches
+            sec = kt[dom]["us_avg"] * 1e-6
+            achieved = alg_per_launch / sec / 1e9
+            own_gbs = own * updates / launches / sec / 1e9
             rec["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": achieved,
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": achieved / HBM_PEAK_GBS,
                                "traffic": measured_traffic(w.name, dom),
                                "alg_bytes_per_launch": alg_per_launch,
-                               "bytes_per_particle": per, "us_per_launch": kt[dom]["us_avg"]}
+                               "bytes_per_particle": gb,
+                               "alg_bytes_source": "gradient evaluation per particle-update: record 8 + "
+                                                   "intensity + face labels 3.4 + sorted record write 8 "
+                                                   "+ Sobolev gradient write 4",
+                               "frac_of_copy": achieved / copy["gbs"],
+                               "kernel_own_bytes_per_particle": own,
+                               "kernel_own_achieved": own_gbs,
+                               "kernel_own_frac": own_gbs / HBM_PEAK_GBS,
+                               "us_per_launch": kt[dom]["us_avg"]}
         else:
             rec["roofline"] = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None,
                                "unit": None, "frac": None, "traffic": None}
         g_ms = kt["k_l2diff"]["ms_total"] + kt["k_sobolev"]["ms_total"]
         g_rate = updates / (g_ms * 1e-3)
-        gb = grad_eval_bytes(w)
         rec["gradient_eval"] = {"us_per_iter": 1e3 * g_ms / a.steps,
                                 "updates_per_s": g_rate, "bytes_per_update": gb,
-                                "hbm_frac": gb * g_rate / 1e9 / HBM_PEAK_GBS}
+                                "hbm_frac": gb * g_rate / 1e9 / HBM_PEAK_GBS,
+                                "frac_of_copy": gb * g_rate / 1e9 / copy["gbs"]}
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(rec), flush=True)

@@ -162,7 +162,11 @@ int32_t sobolev_smooth(sobrc_ctx* ctx, const float* d_dE_l2, float* d_dE_h1, voi
  * int32).  Asynchronous, no host synchronisation.  If the new particle set
  * would exceed max_particles the step is rolled back on the device and the
  * context reports ECAPACITY from its next synchronising call (ctx_sync, run,
- * get_particles); further steps do nothing until a new init_labels. */
+ * get_particles); further steps do nothing until a new init_labels.  The
+ * roll-back restores the labels, the particle set and the region statistics;
+ * compute_l2_diff and sobolev_smooth do not run on the restored state: they
+ * write NaN for every particle until init_labels, and return ECAPACITY once a
+ * synchronising call has reported the overflow. */
 int32_t step(sobrc_ctx* ctx, int32_t mode, int32_t* d_nflips, void* stream);
 
 /* One iteration with a caller-supplied gradient instead of the computed one:
@@ -261,9 +265,12 @@ int32_t batch_run(sobrc_batch* batch, int32_t max_iters, double flip_tol, int32_
  * once (one stream each): batch_launch_iters enqueues `iters` iterations of
  * every live slot (each stops on its own tolerance) without synchronising;
  * batch_collect synchronises `stream`, writes per slot (n_slots entries each,
- * may be NULL) the iterations committed since its init_labels and whether it
- * is stopped (tolerance met or an error), clears the tolerance stops, and
- * returns the first error status of a slot. */
+ * may be NULL) the iterations committed since its init_labels and its state
+ * (h_stopped: 0 running, 1 stopped at its tolerance, or the slot's negative
+ * SOBRC_E* status, e.g. SOBRC_ECAPACITY after a rolled-back step), clears the
+ * tolerance stops, and returns the first error status of a slot.  A failed
+ * slot does nothing more until its context leaves the batch and is
+ * re-initialised; the other slots are unaffected. */
 int32_t batch_launch_iters(sobrc_batch* batch, int32_t iters, double flip_tol, int32_t mode,
                            void* stream);
 int32_t batch_collect(sobrc_batch* batch, int32_t* h_iters, int32_t* h_stopped, void* stream);

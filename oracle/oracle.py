@@ -32,6 +32,11 @@ class Params(C.Structure):
     ]
 
 
+class Auto(C.Structure):
+    _fields_ = [("t", C.c_int32), ("grad", C.c_int32), ("osc_prev", C.c_int32),
+                ("cycle_prev", C.c_int32), ("switch_iter", C.c_int32)]
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
@@ -71,6 +76,10 @@ def lib():
         L.ora_run.restype = C.c_int32
         L.ora_run.argtypes = [P(Params), C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                               C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_auto_init.restype = None
+        L.ora_auto_init.argtypes = [P(Auto), C.c_int32]
+        L.ora_auto_update.restype = C.c_int32
+        L.ora_auto_update.argtypes = [P(Auto), C.c_int32, C.c_double, C.c_int64, C.c_int64, C.c_int64]
         L.ora_reversals.restype = C.c_int64
         L.ora_reversals.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
         L.ora_simple.restype = C.c_int32
@@ -260,6 +269,34 @@ def reversals(L_prev, L_next, stamp, t):
     Lp, Ln = _lab(L_prev), _lab(L_next)
     assert stamp.dtype == np.uint32 and stamp.flags.c_contiguous and stamp.size == Lp.size
     return lib().ora_reversals(Lp.size, _ptr(Lp), _ptr(Ln), _ptr(stamp), int(t))
+
+
+class AutoRule:
+    """ora_auto_init / ora_auto_update: the gradient-mode switch and the stop
+    of a run, fed one iteration's (N_t, flips, reversals) at a time."""
+
+    def __init__(self, mode=MODE_AUTO, tol=0.0):
+        self.mode, self.tol = int(mode), float(tol)
+        self.s = Auto()
+        lib().ora_auto_init(C.byref(self.s), self.mode)
+
+    def update(self, n, flips, reversals) -> bool:
+        """Iteration t = self.t done; True if the run stops after it."""
+        return bool(lib().ora_auto_update(C.byref(self.s), self.mode, self.tol, int(n), int(flips),
+                                          int(reversals)))
+
+    @property
+    def t(self):
+        return self.s.t
+
+    @property
+    def grad(self):
+        """Gradient mode of the next iteration (MODE_SOBOLEV or MODE_L2)."""
+        return self.s.grad
+
+    @property
+    def switch_iter(self):
+        return self.s.switch_iter
 
 
 def energy_pc(P: Params, I, L) -> float:

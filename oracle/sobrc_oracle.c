@@ -761,6 +761,34 @@ int64_t ora_reversals(int64_t nvox, const int32_t* L_prev, const int32_t* L_next
     return back;
 }
 
+void ora_auto_init(ora_auto* s, int32_t mode)
+{
+    s->t = 0;
+    s->grad = mode == ORA_MODE_L2 ? ORA_MODE_L2 : ORA_MODE_SOBOLEV;
+    s->osc_prev = 0;
+    s->cycle_prev = 0;
+    s->switch_iter = -1;
+}
+
+int32_t ora_auto_update(ora_auto* s, int32_t mode, double tol, int64_t n, int64_t flips,
+                        int64_t reversals)
+{
+    const int32_t t = s->t;
+    const int osc = flips > 0 && 2 * reversals >= flips;
+    const int cycle = flips > 0 && reversals == flips; /* every flip undoes the previous iteration's */
+    /* iterations t - 1 and t both ran with L2 gradients after the switch */
+    const int l2_both = s->switch_iter >= 0 && t - 1 >= s->switch_iter;
+    const int stop_cycle = mode == ORA_MODE_AUTO && tol > 0.0 && l2_both && cycle && s->cycle_prev;
+    if (mode == ORA_MODE_AUTO && s->grad == ORA_MODE_SOBOLEV && osc && s->osc_prev) {
+        s->grad = ORA_MODE_L2;
+        s->switch_iter = t + 1;
+    }
+    s->osc_prev = osc;
+    s->cycle_prev = cycle;
+    s->t = t + 1;
+    return (double)flips < tol * (double)n || stop_cycle;
+}
+
 int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
                 int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f,
                 int64_t* hist_b, int32_t* switch_iter)
@@ -768,39 +796,25 @@ int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
     int64_t nvox = (int64_t)P->nx * P->ny * P->nz;
     int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * (size_t)nvox);
     uint32_t* stamp = (uint32_t*)calloc((size_t)nvox, sizeof(uint32_t));
-    int32_t grad = mode == ORA_MODE_L2 ? ORA_MODE_L2 : ORA_MODE_SOBOLEV;
-    if (switch_iter)
-        *switch_iter = -1;
-    int osc_prev = 0, cycle_prev = 0;
-    int32_t first_l2 = -1; /* first iteration run with L2 gradients in AUTO mode */
-    int32_t t = 0;
-    while (t < max_iters) {
+    ora_auto st;
+    ora_auto_init(&st, mode);
+    while (st.t < max_iters) {
+        const int32_t t = st.t;
         int64_t flips = 0;
         memcpy(prev, L, sizeof(int32_t) * (size_t)nvox);
-        int64_t np = ora_step(P, I, L, grad, 0, NULL, NULL, NULL, NULL, NULL, &flips);
+        int64_t np = ora_step(P, I, L, st.grad, 0, NULL, NULL, NULL, NULL, NULL, &flips);
         int64_t back = ora_reversals(nvox, prev, L, stamp, t);
         if (hist_n) hist_n[t] = np;
         if (hist_f) hist_f[t] = flips;
         if (hist_b) hist_b[t] = back;
-        int osc = flips > 0 && 2 * back >= flips;
-        int cycle = flips > 0 && back == flips; /* every flip undoes the previous iteration's */
-        int l2_both = first_l2 >= 0 && t - 1 >= first_l2; /* t - 1 and t ran with L2 gradients */
-        int stop_osc = mode == ORA_MODE_AUTO && tol > 0.0 && l2_both && cycle && cycle_prev;
-        if (mode == ORA_MODE_AUTO && grad == ORA_MODE_SOBOLEV && osc && osc_prev) {
-            grad = ORA_MODE_L2;
-            first_l2 = t + 1;
-            if (switch_iter)
-                *switch_iter = t + 1;
-        }
-        osc_prev = osc;
-        cycle_prev = cycle;
-        ++t;
-        if ((double)flips < tol * (double)np || stop_osc)
+        if (ora_auto_update(&st, mode, tol, np, flips, back))
             break;
     }
+    if (switch_iter)
+        *switch_iter = st.switch_iter;
     free(prev);
     free(stamp);
-    return t;
+    return st.t;
 }
 
 double ora_energy_pc(const ora_params* P, const double* I, const int32_t* L)

@@ -139,15 +139,37 @@ int64_t ora_accept_ranked(const ora_params* P, int32_t* L, int64_t np, const int
 int64_t ora_reversals(int64_t nvox, const int32_t* L_prev, const int32_t* L_next,
                       uint32_t* stamp, int64_t t);
 
+/* The AUTO gradient-mode rule, one iteration at a time (reading: the paper
+ * only says that the oscillation near an energy extremum is easily detected
+ * and that the optimizer then returns to L2-type gradients).  An iteration
+ * oscillates when flips > 0 and 2 * reversals >= flips; it cycles when
+ * flips > 0 and reversals == flips.  In ORA_MODE_AUTO, the first iteration t
+ * that oscillates right after an oscillating iteration t - 1 makes every
+ * later iteration use L2-type gradients (switch_iter = t + 1).  A run stops
+ * after iteration t when flips < tol * N_t, or (AUTO, tol > 0) when t - 1 and
+ * t both ran with L2 gradients and both cycled.
+ * ora_auto_init starts a run; ora_auto_update takes iteration s->t's
+ * particle count, flips and reversals, advances s->t and returns 1 when the
+ * run stops after that iteration.  s->grad is the gradient mode
+ * (ORA_MODE_SOBOLEV or ORA_MODE_L2) of the next iteration. */
+typedef struct {
+    int32_t t;           /* iterations done */
+    int32_t grad;        /* gradient of iteration t */
+    int32_t osc_prev;    /* iteration t - 1 oscillated */
+    int32_t cycle_prev;  /* iteration t - 1 cycled */
+    int32_t switch_iter; /* first iteration with L2 gradients in AUTO mode, -1: none */
+} ora_auto;
+void ora_auto_init(ora_auto* s, int32_t mode);
+int32_t ora_auto_update(ora_auto* s, int32_t mode, double tol, int64_t n, int64_t flips,
+                        int64_t reversals);
+
 /* Repeat ora_step until max_iters or nflips < tol * N_t.  Per-iteration N_t,
  * flips and reversals go to hist_n / hist_f / hist_b (max_iters entries
  * each, may be NULL).  An iteration oscillates when flips > 0 and
  * 2 * reversals >= flips.  In ORA_MODE_AUTO the first iteration t that
  * oscillates right after an oscillating iteration t - 1 switches every later
  * iteration to L2-type gradients; *switch_iter receives t + 1 (or -1: no
- * switch; may be NULL).  With tol > 0, an AUTO run also stops after two
- * iterations in a row that both ran with L2 gradients and in which every
- * flip was a reversal (flips > 0 and reversals == flips).
+ * switch; may be NULL).  The switch and the stops follow ora_auto_update.
  * Returns iterations done. */
 int32_t ora_run(const ora_params* P, const double* I, int32_t* L, int32_t mode,
                 int32_t max_iters, double tol, int64_t* hist_n, int64_t* hist_f,

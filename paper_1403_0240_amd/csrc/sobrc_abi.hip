@@ -362,6 +362,7 @@ struct sobrc_ctx {
     const void* image = nullptr;
     int cur = 0;
     bool initialized = false;
+    unsigned seen_err = 0;  // device error bits a synchronising call has read (cleared by init_labels)
     // hipGraph of two consecutive steps, per start parity and mode
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2][3] = {};  // [start parity][gradient mode]
@@ -431,6 +432,7 @@ int32_t read_state(sobrc_ctx* c, DevState* h, hipStream_t s)
 {
     SOBRC_HIP(hipMemcpyAsync(h, c->b.ds, sizeof(DevState), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     SOBRC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    c->seen_err |= h->err;
     return SOBRC_OK;
 }
 
@@ -602,6 +604,7 @@ int32_t init_labels(sobrc_ctx* c, const void* d_image, const int32_t* d_labels, 
         return fail(SOBRC_EINVAL, "image and labels must be device pointers");
     hipStream_t s = (hipStream_t)stream;
     c->initialized = false;
+    c->seen_err = 0;
     drop_graphs(c);  // graphs hold the image pointer and the intensity scale
     c->image = d_image;
     Geom& g = c->g;
@@ -664,6 +667,8 @@ int32_t compute_l2_diff(sobrc_ctx* c, float* d_dE_l2, void* stream)
         return fail(SOBRC_ESTATE, "compute_l2_diff before init_labels");
     if (!d_dE_l2)
         return fail(SOBRC_EINVAL, "output is NULL");
+    if (c->seen_err & kErrCapacity)
+        return fail(SOBRC_ECAPACITY, "a step overflowed the particle capacity: init_labels first");
     hipStream_t s = (hipStream_t)stream;
     if (c->g.psf)
         SOBRC_TRY(timed(c, SOBRC_K_DECONV, s, "k_deconv",
@@ -682,6 +687,8 @@ int32_t sobolev_smooth(sobrc_ctx* c, const float* d_in, float* d_out, void* stre
         return fail(SOBRC_EINVAL, "input and output must be device pointers");
     if (d_in == d_out)
         return fail(SOBRC_EINVAL, "input and output must be distinct buffers (Jacobi update)");
+    if (c->seen_err & kErrCapacity)
+        return fail(SOBRC_ECAPACITY, "a step overflowed the particle capacity: init_labels first");
     hipStream_t s = (hipStream_t)stream;
     return timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
                  [&] { return launch_sobolev(c->g, c->b, c->sw, c->cur, d_in, d_out, 0, 1, s); });
@@ -1195,14 +1202,17 @@ int32_t batch_collect(sobrc_batch* B, int32_t* h_iters, int32_t* h_stopped, void
     int32_t status = SOBRC_OK;
     for (int i = 0; i < B->nslot; ++i) {
         const bool live = B->slot[i] != nullptr;
-        if (live)
+        const int32_t si = live ? slot_status(st[i]) : SOBRC_OK;
+        if (live) {
             B->slot[i]->cur = (int)(st[i].x & 1u);
+            B->slot[i]->seen_err |= st[i].z;
+        }
         if (h_iters)
             h_iters[i] = live ? (int32_t)st[i].x : 0;
         if (h_stopped)
-            h_stopped[i] = live && (st[i].y || st[i].z) ? 1 : 0;
-        if (live && status == SOBRC_OK)
-            status = slot_status(st[i]);
+            h_stopped[i] = si != SOBRC_OK ? si : (live && st[i].y ? 1 : 0);
+        if (status == SOBRC_OK)
+            status = si;
     }
     if (B->has_class) {
         BatchTab t{B->d_desc, B->d_par, B->d_off, B->d_tpre, B->nslot};

@@ -74,6 +74,24 @@ __device__ __forceinline__ bool stopped(const DevState* ds)
     return (ds->err | ds->converged) != 0;
 }
 
+// A step that overflowed the particle capacity was rolled back: labels,
+// records and region sums are those of the previous state again, but the
+// emission slots of its dirty tiles and the per-label table still describe
+// the rejected state.  The stand-alone gradient kernels then write NaN for
+// every particle instead of reading them (until init_labels clears the error).
+__device__ __forceinline__ bool fill_nan_after_rollback(const Bufs& b, int cur, float* out, VB vb)
+{
+    const DevState* ds = b.ds;
+    if (!(ds->err & kErrCapacity))
+        return false;
+    const unsigned long long n = ds->n[cur];
+    const float qnan = __int_as_float(0x7fc00000);
+    for (unsigned long long i = (unsigned long long)vb.id * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)vb.n * blockDim.x)
+        out[i] = qnan;
+    return true;
+}
+
 // ------------------------------------------------------------ init kernels
 
 __global__ __launch_bounds__(kBlock) void k_init_labels(Geom g, Bufs b, const int32_t* __restrict__ lin_labels,
@@ -1189,6 +1207,8 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
     }
     if (gated && stopped(ds))
         return;
+    if (!gated && fill_nan_after_rollback(b, cur, out, vb))
+        return;
     unsigned n = ds->n[cur];
     const uint2* rec = b.rec[cur];
     long long nxy = (long long)g.nx * g.ny;
@@ -1302,6 +1322,8 @@ __device__ __forceinline__ void l2diff_ps_tile_body(const Geom& g, const Bufs& b
         ds->lmode = (ds->lmode & ~1u) | (ds->switch_it != 0 ? 1u : 0u);
     }
     if (gated && stopped(ds))
+        return;
+    if (!gated && fill_nan_after_rollback(b, cur, out, vb))
         return;
     const int R = g.R, rz = g.ndim == 3 ? R : 0;
     const int TX = 1 << g.tsx, TY = 1 << g.tsy, TZ = 1 << g.tsz;
@@ -1537,6 +1559,8 @@ __device__ __forceinline__ void sobolev_generic_body(const Geom& g, const Bufs& 
         return;
     if ((gated & kAuto) && (b.ds->lmode & 1u))
         return;  // L2 gradients in force: no smoothing
+    if (!(gated & kGate) && fill_nan_after_rollback(b, cur, out, vb))
+        return;
     unsigned a0, a1;
     xcd_chunk(b.ds->n_active[cur], vb, a0, a1);
     for (unsigned ai = a0; ai < a1; ++ai)
@@ -1832,6 +1856,8 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
 template <int ND, int H, bool FULL>
 __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* __restrict__ in, float* __restrict__ out, int gated, VB vb)
 {
+    if (!(gated & kGate) && fill_nan_after_rollback(b, cur, out, vb))
+        return;
     unsigned a0, a1;
     xcd_chunk(b.ds->n_active[cur], vb, a0, a1);
     brick_range<ND, H, FULL>(g, b, sw, cur, in, out, gated, a0, a1);

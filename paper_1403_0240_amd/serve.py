@@ -37,8 +37,9 @@ class Request:
     iterations: int = 0
     labels: np.ndarray | None = None
     switch_iter: int = -1
-    error: str | None = None
+    error: str | None = None     # set when the request failed (its labels are those it stopped at)
     footprint: int = 0
+    capacity: int | None = None  # particle capacity (None: default_capacity of the image)
 
     @property
     def latency(self) -> float:
@@ -109,7 +110,9 @@ class Server:
             # such contexts are not batched: run them with sobrc.run on their own
             raise ValueError(f"request {req.rid}: topological control and the deconvolving model "
                              f"are not served in batches")
-        req.footprint = footprint(req.work, default_capacity(req.work))
+        if req.capacity is None:
+            req.capacity = default_capacity(req.work)
+        req.footprint = footprint(req.work, req.capacity)
         if req.footprint > self.budget:
             raise ValueError(f"request {req.rid} needs {req.footprint} bytes > budget {self.budget}")
         self.waiting.append(req)
@@ -133,7 +136,7 @@ class Server:
                 return
             self.waiting.popleft()
             w = req.work
-            cap = default_capacity(w)
+            cap = req.capacity
             with torch.cuda.stream(self.admit_stream):
                 ctx, img, lab = S.from_workload(w, max_particles=cap)
                 S.init_labels(ctx, img, lab, stream=self.admit_stream)
@@ -154,13 +157,17 @@ class Server:
                 job.req.admitted = self.now()
 
     # ---------------------------------------------------------------- ticks
-    def _retire(self, pool: _Pool, k: int):
+    def _retire(self, pool: _Pool, k: int, error: str | None = None):
         job = pool.jobs[k]
         req = job.req
         pool.batch.set(k, None, stream=pool.stream)
-        req.labels = S.get_labels(job.ctx, stream=pool.stream).cpu().numpy()
+        # the label copy-out runs on the pool's stream: allocate, launch and
+        # copy to the host there, so the host copy waits for the kernel
+        with torch.cuda.stream(pool.stream):
+            req.labels = S.get_labels(job.ctx, stream=pool.stream).cpu().numpy()
         req.switch_iter = S.gradient_switch(job.ctx, stream=pool.stream)
         req.iterations = int(pool.iters[k])
+        req.error = error
         req.done = self.now()
         pool.jobs[k] = None
         self.used -= req.footprint
@@ -182,10 +189,14 @@ class Server:
             busy.append(pool)
         self._prepare()
         for pool in busy:
-            it, stopped = pool.batch.collect(stream=pool.stream)
+            # a slot's own failure (e.g. its particle set outgrew its
+            # capacity) ends that request only
+            it, state = pool.batch.collect(stream=pool.stream, slot_errors=True)
             for k, job in pool.live():
                 pool.iters[k] = it[k]
-                if stopped[k] or it[k] >= self.max_iters:
+                if state[k] < 0:
+                    self._retire(pool, k, error=f"sobrc error {int(state[k])} after {int(it[k])} iterations")
+                elif state[k] or it[k] >= self.max_iters:
                     self._retire(pool, k)
         # every pool is idle: place what was prepared, then fill freed slots
         self._place()
@@ -194,11 +205,14 @@ class Server:
         return any(p.live() for p in self.pools.values())
 
     def serve(self, stream_of_requests, realtime: bool = True):
-        """Run a list of (arrival seconds, Workload) to completion.  With
-        realtime, each request is submitted when the clock reaches its arrival
-        time; otherwise all arrive at time 0 (saturation)."""
+        """Run a list of (arrival seconds, Workload) or (arrival seconds,
+        Workload, particle capacity) to completion.  With realtime, each
+        request is submitted when the clock reaches its arrival time;
+        otherwise all arrive at time 0 (saturation)."""
         pending = collections.deque(
-            Request(k, w, float(t) if realtime else 0.0) for k, (t, w) in enumerate(stream_of_requests))
+            Request(k, item[1], float(item[0]) if realtime else 0.0,
+                    capacity=item[2] if len(item) > 2 else None)
+            for k, item in enumerate(stream_of_requests))
         self.t0 = time.perf_counter()
         while pending or self.waiting or any(p.live() for p in self.pools.values()):
             while pending and pending[0].arrival <= self.now():

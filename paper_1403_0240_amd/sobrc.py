@@ -385,14 +385,19 @@ class Batch:
         """Enqueue iterations without synchronising (see collect)."""
         _check(lib().batch_launch_iters(self.handle, iters, float(flip_tol), mode, _stream(stream)))
 
-    def collect(self, stream=None):
-        """Synchronise; per slot: iterations since init_labels, stopped flag."""
+    def collect(self, stream=None, slot_errors=False):
+        """Synchronise; per slot: iterations since init_labels and stopped flag
+        (tolerance met or an error).  With slot_errors=True a slot's own error
+        does not raise: the second array then holds each slot's state code
+        (0 running, 1 stopped at its tolerance, a negative error code)."""
         import numpy as np
         it = np.zeros(self.n_slots, np.int32)
         st = np.zeros(self.n_slots, np.int32)
-        _check(lib().batch_collect(self.handle, it.ctypes.data_as(C.c_void_p),
-                                   st.ctypes.data_as(C.c_void_p), _stream(stream)))
-        return it, st.astype(bool)
+        code = lib().batch_collect(self.handle, it.ctypes.data_as(C.c_void_p),
+                                   st.ctypes.data_as(C.c_void_p), _stream(stream))
+        if code != OK and not (slot_errors and (st == code).any()):
+            _check(code)
+        return (it, st) if slot_errors else (it, st != 0)
 
     def set_shape(self, part_chunk=0, lg_range=0, sob_tiles=0, stream=None):
         _check(lib().batch_set_shape(self.handle, part_chunk, lg_range, sob_tiles, _stream(stream)))

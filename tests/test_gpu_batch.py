@@ -1,9 +1,11 @@
 """Batched launches (many contexts, one set of launches per iteration) against
-stand-alone runs of the same contexts.
+stand-alone runs of the same contexts, and against the oracle.
 
 A slot's results must be bit-identical to its stand-alone run: label field,
 particle set in context order, region statistics and per-iteration telemetry.
-Stand-alone runs are themselves held to the oracle by test_gpu_parity.py.
+Slots are also checked at every batched iteration against the oracle
+stepping from the slot's own labels (particle sets exact, gradients within
+1e-5, labels outside the decision margin).
 """
 import numpy as np
 import pytest
@@ -13,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1403_0240_amd import sobrc as S  # noqa: E402
 from paper_1403_0240_amd import workloads as W  # noqa: E402
+from shadow import Shadow  # noqa: E402
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -81,6 +84,57 @@ def test_batch_equals_standalone(dims, mode):
         ref, _, _ = make_ctx(w)
         S.run(ref, iters + 3, 0.0, mode)
         assert_same(snapshot(c), snapshot(ref), "after batched steps")
+    B.close()
+
+
+def batch_shadow_steps(ora, B, ctxs, ws, shadowed, iters, mode):
+    """iters batched steps; the slots in `shadowed` are checked against the
+    oracle at every one."""
+    shadows = [Shadow(ora, ws[k], ctxs[k], mode) for k in shadowed]
+    for _ in range(iters):
+        states = [sh.pre() for sh in shadows]
+        B.step(mode)
+        for sh, st in zip(shadows, states):
+            sh.post(st)
+    for k, sh in zip(shadowed, shadows):
+        sh.report(f"slot {k}")
+        assert sh.checked == iters
+    return shadows
+
+
+@pytest.mark.parametrize("dims", ["2d", "3d"])
+@pytest.mark.parametrize("mode", [S.MODE_SOBOLEV, S.MODE_L2])
+def test_batch_slots_match_oracle(ora, dims, mode):
+    """Three slots of a batch (of different sizes and, in 3D, image types)
+    checked against the oracle at each of nine batched iterations."""
+    ws = small_2d() if dims == "2d" else small_3d()
+    print(f"[batch oracle {dims} mode={mode} n={len(ws)}]", flush=True)
+    B = S.Batch(len(ws))
+    ctxs = [make_ctx(w)[0] for w in ws]
+    for k, c in enumerate(ctxs):
+        B.set(k, c)
+    batch_shadow_steps(ora, B, ctxs, ws, (0, 1, len(ws) - 1), 9, mode)
+    B.close()
+
+
+def test_batch2d_64_slots_match_oracle(ora):
+    """The batched benchmark workload (64 images of 128..1024 pixels a side):
+    the smallest, a middle and the largest image checked against the oracle
+    at every one of six batched iterations, with all 64 slots live."""
+    ws = W.batch2d()
+    ctxs = []
+    for w in ws:
+        c, img, lab = S.from_workload(w)
+        S.init_labels(c, img, lab)
+        ctxs.append(c)
+    sizes = [w.labels.size for w in ws]
+    order = np.argsort(sizes)
+    shadowed = (int(order[0]), int(order[len(order) // 2]), int(order[-1]))
+    print(f"[batch2d_64 oracle: slots {shadowed}]", flush=True)
+    B = S.Batch(len(ws))
+    for k, c in enumerate(ctxs):
+        B.set(k, c)
+    batch_shadow_steps(ora, B, ctxs, ws, shadowed, 6, S.MODE_SOBOLEV)
     B.close()
 
 

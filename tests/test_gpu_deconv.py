@@ -13,7 +13,13 @@ pytestmark = pytest.mark.gpu
 
 from paper_1403_0240_amd import sobrc as S  # noqa: E402
 from paper_1403_0240_amd import workloads as W  # noqa: E402
-from test_gpu_parity import REL_GRAD, compare_labels, gpu_state, match_order, rel_err  # noqa: E402
+from shadow import REL_GRAD, Shadow, match_order, rel_err  # noqa: E402
+
+
+def gpu_state(w, cap=None):
+    ctx, img, lab = S.from_workload(w, max_particles=cap)
+    S.init_labels(ctx, img, lab)
+    return ctx, img, lab
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -57,38 +63,26 @@ def test_deconv_gradients(ora, name):
 
 @pytest.mark.parametrize("name", ["2d_s1.5", "3d_s1", "2d_two_labels"])
 def test_deconv_trajectory(ora, name):
+    """Eight iterations, each checked against the oracle stepping from the
+    GPU's labels (gradients on every particle, labels outside the margin)."""
     w = CASES[name]()
     print(f"[case {name} trajectory]", flush=True)
-    P = ora.params_of(w)
     ctx, img, lab = gpu_state(w)
-    L_o = w.labels.copy()
-    for t in range(8):
-        L_next, info = ora.step(P, w.image, L_o, ora.MODE_SOBOLEV)
-        match_order(ctx, info["lin"], info["b"])
-        S.step(ctx, S.MODE_SOBOLEV)
-        nd = compare_labels(S.get_labels(ctx).cpu().numpy(), L_next, info["lin"], info["dE_h1"])
-        if nd:
-            print(f"  step {t}: {nd} marginal flips differ; stopping comparison")
-            return
-        L_o = L_next
+    sh = Shadow(ora, w, ctx).run(8)
+    sh.report(name)
+    assert sh.checked == 8
 
 
-def test_deconv_full_size_first_step(ora):
-    """The 512^2 scene with a sigma = 15 PSF: gradients on every particle and
-    the first step's labels."""
+def test_deconv_full_size_first_steps(ora):
+    """The 512^2 scene with a sigma = 15 PSF: particle set, L2 and Sobolev
+    gradients on every particle and the labels of the first three
+    iterations, each checked from the GPU's labels."""
     w = W.make("deconv2d_512")
     print("[case deconv2d_512]", flush=True)
-    P = ora.params_of(w, threads=8)
     ctx, img, lab = gpu_state(w)
-    lin_o, a_o, b_o = ora.particles(P, w.labels)
-    perm, lin, a, b = match_order(ctx, lin_o, b_o)
-    dl2 = S.compute_l2_diff(ctx)
-    o_l2 = ora.l2diff(P, w.image, w.labels, lin_o, a_o, b_o)
-    assert rel_err(dl2[: len(lin)].cpu().numpy()[perm], o_l2) <= REL_GRAD
-    L_next, info = ora.step(P, w.image, w.labels, ora.MODE_SOBOLEV)
-    S.step(ctx, S.MODE_SOBOLEV)
-    nd = compare_labels(S.get_labels(ctx).cpu().numpy(), L_next, info["lin"], info["dE_h1"])
-    print(f"  N={len(lin)} marginal label differences: {nd}")
+    sh = Shadow(ora, w, ctx).run(3)
+    sh.report("deconv2d_512")
+    assert sh.checked == 3
 
 
 def test_psf_contexts_are_not_batched():
@@ -105,23 +99,13 @@ def test_psf_contexts_are_not_batched():
 
 def test_deconv_with_topological_control(ora):
     """The deconvolving gradient driving the ranked, controlled acceptance:
-    trajectory against the oracle until the first marginal decision."""
-    from test_gpu_topology import MARGIN, topo_marginal
+    eight iterations, each checked against the oracle from the GPU's labels
+    (a ranked decision is marginal near small or nearly tied gradients)."""
+    from test_gpu_topology import topo_shadow_marginal
     w = _case(58, (36, 44), 2.0, n_labels=3, lam=0.2)
     w.topo = S.TOPO_SIMPLE
     print("[case deconv + topo]", flush=True)
-    P = ora.params_of(w)
     ctx, img, lab = gpu_state(w)
-    L_o = w.labels.copy()
-    for t in range(8):
-        L_next, info = ora.step(P, w.image, L_o, ora.MODE_SOBOLEV)
-        S.step(ctx, S.MODE_SOBOLEV)
-        L_g = S.get_labels(ctx).cpu().numpy()
-        diff = L_g != L_next
-        if diff.any():
-            g = info["dE_h1"]
-            marg = topo_marginal(w.labels.shape, info["lin"], g, MARGIN * np.abs(g).max())
-            assert not (diff & ~marg).any(), f"step {t}: non-marginal differences"
-            print(f"  step {t}: {int(diff.sum())} marginal differences; stopping comparison")
-            return
-        L_o = L_next
+    sh = Shadow(ora, w, ctx, marginal=topo_shadow_marginal(w)).run(8)
+    sh.report("deconv + topo")
+    assert sh.checked == 8

@@ -20,9 +20,8 @@ pytestmark = pytest.mark.gpu
 
 from paper_1403_0240_amd import sobrc as S  # noqa: E402
 from paper_1403_0240_amd import workloads as W  # noqa: E402
-
-REL_GRAD = 1e-5
-MARGIN = 1e-4
+from shadow import (REL_GRAD, Shadow, compare_labels, gpu_particles, match_order,  # noqa: E402,F401
+                    oracle_threads, rel_err)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -32,57 +31,10 @@ def _gpu():
     S.lib()
 
 
-def _keys(lin, b):
-    return np.asarray(lin, np.int64) * 65536 + np.asarray(b, np.int64)
-
-
 def gpu_state(w, cap=None):
     ctx, img, lab = S.from_workload(w, max_particles=cap)
     S.init_labels(ctx, img, lab)
     return ctx, img, lab
-
-
-def gpu_particles(ctx):
-    lin, a, b = (t.cpu().numpy() for t in S.get_particles(ctx))
-    return lin.astype(np.int64), a, b
-
-
-def match_order(ctx, lin_o, b_o):
-    """Permutation taking GPU (context) order to oracle order; asserts the two
-    particle sets are identical."""
-    lin, a, b = gpu_particles(ctx)
-    gk = _keys(lin, b)
-    perm = np.argsort(gk, kind="stable")
-    ok = _keys(lin_o, b_o)
-    assert len(gk) == len(ok), f"particle count {len(gk)} != oracle {len(ok)}"
-    assert np.array_equal(gk[perm], ok), "particle sets differ"
-    return perm, lin, a, b
-
-
-def rel_err(g, o):
-    scale = np.abs(o).max() if len(o) else 1.0
-    return float(np.abs(g - o).max() / scale) if len(o) else 0.0
-
-
-def marginal_pixels(lin, g, thr):
-    lin = np.asarray(lin)
-    m = set(lin[np.abs(g) <= thr].tolist())
-    order = np.lexsort((g, lin))
-    ls, gs = lin[order], g[order]
-    for k in range(1, len(ls)):
-        if ls[k] == ls[k - 1] and gs[k - 1] < 0 and gs[k] - gs[k - 1] <= thr:
-            m.add(int(ls[k]))
-    return m
-
-
-def compare_labels(L_gpu, L_ora, lin, g):
-    """Labels agree at all non-marginal pixels; returns the marginal flips."""
-    thr = MARGIN * (np.abs(g).max() if len(g) else 1.0)
-    marg = marginal_pixels(lin, g, thr)
-    diff = np.flatnonzero(L_gpu.reshape(-1) != L_ora.reshape(-1))
-    bad = [int(i) for i in diff if int(i) not in marg]
-    assert not bad, f"{len(bad)} non-marginal pixels differ, e.g. {bad[:5]}"
-    return len(diff)
 
 
 CASES = {
@@ -163,66 +115,48 @@ def test_particles_and_gradients(ora, name):
 
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_step_trajectory(ora, name):
-    """Independent GPU and oracle trajectories: particle sets, statistics and
-    labels agree after every step until the first marginal flip (each side
-    evolves from its own state, so a marginal flip is where comparison ends)."""
+    """Twelve iterations, each checked against the oracle stepping from the
+    GPU's own labels: particle set, both gradients on every particle, labels
+    outside the margin, flips, reversals and region statistics."""
     w = CASES[name]()
     print(f"[case {name} shape={w.image.shape}]", flush=True)
-    P = ora.params_of(w)
     ctx, img, lab = gpu_state(w, cap=CAPS.get(name))
-    L_o = w.labels.copy()
-    nfl = torch.zeros(1, dtype=torch.int32, device="cuda")
-    steps = 12
-    for t in range(steps):
-        L_next, info = ora.step(P, w.image, L_o, ora.MODE_SOBOLEV)
-        match_order(ctx, info["lin"], info["b"])
-        S.step(ctx, S.MODE_SOBOLEV, nfl)
-        L_g = S.get_labels(ctx).cpu().numpy()
-        nd = compare_labels(L_g, L_next, info["lin"], info["dE_h1"])
-        if nd:
-            print(f"  step {t}: {nd} marginal flips differ; stopping comparison")
-            return
-        assert int(nfl.item()) == info["flips"]
-        n_g, s_g = S.get_region_stats(ctx)
-        n_o, s1_o, _ = ora.region_stats(P, w.image, L_next)
-        assert np.array_equal(n_g, n_o)
-        if w.image.dtype == np.uint16:
-            assert np.array_equal(s_g, s1_o)
-        else:
-            assert np.allclose(s_g, s1_o, rtol=0, atol=1e-6 * max(1.0, np.abs(s1_o).max()))
-        L_o = L_next
-    lin_o, a_o, b_o = ora.particles(P, L_o)
+    sh = Shadow(ora, w, ctx, S.MODE_SOBOLEV).run(12)
+    sh.report(name)
+    assert sh.checked == 12
+    lin_o, a_o, b_o = ora.particles(sh.P, sh.L)
     match_order(ctx, lin_o, b_o)
     hn, hf = S.get_history(ctx)
-    assert len(hn) == steps
+    assert len(hn) == 12
 
 
 def test_l2_mode_and_tolerance_stop(ora):
+    """L2 gradients with a flip tolerance: every iteration checked against
+    the oracle from the GPU's labels up to the stop the tolerance names; a
+    graph-replayed run from the same start stops at the same iteration with
+    the same labels and particle set."""
     w = W.disk2d()
-    P = ora.params_of(w)
-    L_o, t_o, hn, hf = ora.run(P, w.image, w.labels, mode=ora.MODE_L2, max_iters=200, tol=1e-3)
+    print("[case disk2d_128 L2 tol]", flush=True)
     ctx, img, lab = gpu_state(w)
-    t_g = S.run(ctx, 200, 1e-3, S.MODE_L2)
-    L_g = S.get_labels(ctx).cpu().numpy()
-    if (L_g != L_o).any():
-        pytest.skip("trajectories split at a marginal flip")
-    assert t_g == t_o
-    gn, gf = S.get_history(ctx)
-    assert np.array_equal(gn, hn) and np.array_equal(gf, hf)
+    sh = Shadow(ora, w, ctx, S.MODE_L2, tol=1e-3).run(200)
+    sh.report("disk2d_128 L2")
+    assert sh.stopped and sh.checked == sh.steps < 200
+    ctx2, _, _ = gpu_state(w)
+    assert S.run(ctx2, 200, 1e-3, S.MODE_L2) == sh.steps
+    assert np.array_equal(S.get_labels(ctx2).cpu().numpy(), sh.L)
+    gn, gf = S.get_history(ctx2)
+    assert len(gn) == sh.steps
     # the particle set is the one of the final labels, whatever the parity of
     # the stopping iteration
-    lin_o, a_o, b_o = ora.particles(P, L_o)
-    lin, a, b = gpu_particles(ctx)
-    assert set(zip(lin, a, b)) == set(zip(lin_o, a_o, b_o))
-    # further steps after convergence keep working (run resets the stop flag)
-    assert S.run(ctx, 3, 0.0, S.MODE_L2) == 3
-    L3, _, _, _ = ora.run(P, w.image, L_o, mode=ora.MODE_L2, max_iters=3, tol=0.0)
-    if np.array_equal(S.get_labels(ctx).cpu().numpy(), L3):
-        lin3, a3, b3 = ora.particles(P, L3)
-        lin, a, b = gpu_particles(ctx)
-        assert set(zip(lin, a, b)) == set(zip(lin3, a3, b3))
-    S.step(ctx, S.MODE_L2)
-    assert S.particle_count(ctx) == len(ora.particles(P, S.get_labels(ctx).cpu().numpy())[0])
+    lin_o, a_o, b_o = ora.particles(sh.P, sh.L)
+    match_order(ctx2, lin_o, b_o)
+    # further iterations after the stop keep working (run resets the stop flag)
+    assert S.run(ctx2, 3, 0.0, S.MODE_L2) == 3
+    sh.resume(S.MODE_L2, 0.0).run(3)
+    assert sh.checked == sh.steps
+    assert np.array_equal(S.get_labels(ctx2).cpu().numpy(), sh.L)
+    lin3, _, b3 = ora.particles(sh.P, sh.L)
+    match_order(ctx2, lin3, b3)
 
 
 def test_degenerate_support_equals_l2_step(ora):
@@ -312,6 +246,24 @@ def test_capacity_errors_roll_back(ora):
     assert np.array_equal(lin0, lin1) and np.array_equal(b0, b1)
     n_g, _ = S.get_region_stats(ctx)
     assert n_g[1] == (w.labels == 1).sum()
+    # the gradients of the rolled-back state are refused once the overflow
+    # has been reported ...
+    for call in (lambda: S.compute_l2_diff(ctx),
+                 lambda: S.sobolev_smooth(ctx, torch.zeros(330, device="cuda"))):
+        with pytest.raises(S.SobrcError) as e:
+            call()
+        assert e.value.code == S.ECAPACITY
+    # ... and are NaN when asked for before anything synchronised
+    ctx3, img3, lab3 = S.from_workload(w, max_particles=330)
+    S.init_labels(ctx3, img3, lab3)
+    S.step(ctx3)
+    g2 = S.compute_l2_diff(ctx3)
+    g1 = S.sobolev_smooth(ctx3, torch.zeros(330, device="cuda"))
+    n3 = len(lin0)
+    assert torch.isnan(g2[:n3]).all() and torch.isnan(g1[:n3]).all()
+    with pytest.raises(S.SobrcError) as e:
+        S.ctx_sync(ctx3)
+    assert e.value.code == S.ECAPACITY
     # a new init_labels clears the error
     ctx2, img2, lab2 = S.from_workload(w)
     S.init_labels(ctx2, img2, lab2)
@@ -375,58 +327,61 @@ def test_uniform_and_empty_fields(ora):
 @pytest.mark.parametrize("name", ["ellipsoids3d_256", "ellipses2d_1024"])
 def test_full_size_first_step(ora, name):
     """The full-size workloads in the launch configuration the benchmark uses:
-    particle set bit-exact, gradients within the bar on every particle (L2)
-    and on a sample (Sobolev, evaluated one by one in the oracle), labels after
-    one step identical outside the margin."""
+    particle set bit-exact, L2 and Sobolev gradients within the bar on every
+    particle, labels after one step identical outside the margin, and the
+    particle set after the step bit-exact."""
     w = W.make(name)
     print(f"[case {name} shape={w.image.shape}]", flush=True)
-    P = ora.params_of(w, threads=8)
     ctx, img, lab = gpu_state(w)
-    lin_o, a_o, b_o = ora.particles(P, w.labels)
-    perm, lin, a, b = match_order(ctx, lin_o, b_o)
-    dl2 = S.compute_l2_diff(ctx)
-    o_l2 = ora.l2diff(P, w.image, w.labels, lin_o, a_o, b_o)
-    assert rel_err(dl2[: len(lin)].cpu().numpy()[perm], o_l2) <= REL_GRAD
-    dh1 = S.sobolev_smooth(ctx, dl2)[: len(lin)].cpu().numpy()[perm]
-    sel = np.random.default_rng(5).choice(len(lin_o), size=min(20000, len(lin_o)), replace=False)
-    o_h1 = ora.sobolev(P, lin_o, a_o, b_o, o_l2, sel=sel)
-    scale = np.abs(o_h1).max()
-    assert np.abs(dh1[sel] - o_h1).max() <= REL_GRAD * scale
-    L_next, info = ora.step(P, w.image, w.labels, ora.MODE_SOBOLEV)
-    S.step(ctx)
-    nd = compare_labels(S.get_labels(ctx).cpu().numpy(), L_next, info["lin"], info["dE_h1"])
-    print(f"  N={len(lin)} marginal label differences: {nd}")
+    sh = Shadow(ora, w, ctx).run(1)
+    sh.report(name)
+    lin_o, a_o, b_o = ora.particles(sh.P, sh.L)
+    match_order(ctx, lin_o, b_o)
+
+
+# Iterations of the full-size runs compared with the oracle (stepping from the
+# GPU's labels), spread over the first iterations -- the benchmark times the
+# workload's first K iterations from the seeded start -- and over the whole
+# 150-iteration run of the 3D workload.
+SHADOW = {
+    ("ellipsoids3d_256", "early"): (13, [0, 1, 2, 3, 4, 6, 9, 12]),
+    ("ellipsoids3d_256", "mid"): (26, [14, 16, 19, 21, 23, 25]),
+    ("ellipsoids3d_256", "late"): (150, [40, 75, 110, 149]),
+    ("ellipses2d_1024", "early"): (26, list(range(26))),
+    ("ellipses2d_1024", "late"): (200, [50, 100, 150, 199]),
+}
+
+
+@pytest.mark.parametrize("name,window", sorted(SHADOW))
+def test_full_size_shadow(ora, name, window):
+    iters, at = SHADOW[(name, window)]
+    w = W.make(name)
+    print(f"[case {name} shadow {window}: iterations {at}]", flush=True)
+    ctx, img, lab = gpu_state(w)
+    sh = Shadow(ora, w, ctx).run(iters, check_at=set(at))
+    sh.report(f"{name} {window}")
+    assert sh.steps == iters and sh.checked == len(at)
 
 
 @pytest.mark.parametrize("name", ["disk2d_128", "rand3d_u16", "rand2d_ps", "many_labels_2d"])
 def test_auto_mode_matches_oracle(ora, name):
-    """AUTO gradient mode: same per-iteration particle counts, flips and
-    reversals as the oracle, the same switch to L2 gradients, the same stop
-    and final labels (unless the trajectories split at a marginal flip)."""
+    """AUTO gradient mode with a tolerance: every iteration checked against
+    the oracle from the GPU's labels, with the gradient the oracle's AUTO rule
+    names from the GPU's own flip and reversal counts; the GPU switches to L2
+    gradients at the rule's iteration, and a graph-replayed run from the same
+    start stops where the rule stops, with the same labels."""
     w = CASES[name]()
     print(f"[case {name} auto]", flush=True)
-    P = ora.params_of(w)
-    o = ora.run_ex(P, w.image, w.labels, ora.MODE_AUTO, 200, 1e-3)
     cap = max(4096, 2 * w.labels.size)  # at most one particle per pixel and other label
     ctx, img, lab = gpu_state(w, cap=cap)
-    t_g = S.run(ctx, 200, 1e-3, S.MODE_AUTO)
-    L_g = S.get_labels(ctx).cpu().numpy()
-    gn, gf, gb = S.get_history(ctx, reversals=True)
-    if (L_g != o["L"]).any() or t_g != o["t"]:
-        k = next((i for i in range(min(len(gf), len(o["flips"])))
-                  if gf[i] != o["flips"][i] or gn[i] != o["n"][i]), None)
-        pytest.skip(f"trajectories split (first differing iteration {k})")
-    assert np.array_equal(gn, o["n"]) and np.array_equal(gf, o["flips"])
-    assert np.array_equal(gb, o["reversals"])
-    assert S.gradient_switch(ctx) == o["switch"] > 0
-    # step-by-step AUTO iterations (no graphs) follow the same path
+    sh = Shadow(ora, w, ctx, S.MODE_AUTO, tol=1e-3).run(200)
+    sh.report(f"{name} auto")
+    assert sh.stopped and sh.checked == sh.steps
+    assert sh.rule.switch_iter > 0
     ctx2, _, _ = gpu_state(w, cap=cap)
-    for _ in range(o["switch"] + 3):
-        S.step(ctx2, S.MODE_AUTO)
-    n2, f2, b2 = S.get_history(ctx2, reversals=True)
-    k = o["switch"] + 3
-    assert np.array_equal(f2, o["flips"][:k]) and np.array_equal(b2, o["reversals"][:k])
-    assert S.gradient_switch(ctx2) == o["switch"]
+    assert S.run(ctx2, 200, 1e-3, S.MODE_AUTO) == sh.steps
+    assert S.gradient_switch(ctx2) == sh.rule.switch_iter
+    assert np.array_equal(S.get_labels(ctx2).cpu().numpy(), sh.L)
     # a fresh init_labels clears the switch
     S.init_labels(ctx2, img, lab)
     assert S.gradient_switch(ctx2) == -1

@@ -1,11 +1,15 @@
 """Continuous-batching server: each request's result is the same alone and in
-the mix.
+the mix, and the same as the oracle's.
 
 Requests of two kernel geometries (2D and 3D) arrive while others run, wait
 for slots and HBM room, share batches with whatever else is resident, and
 retire on their own.  Each must end with exactly the label field and
-iteration count of its own stand-alone run (AUTO gradients, tolerance stop),
-which test_gpu_parity.py in turn holds to the oracle.
+iteration count of its own stand-alone run (AUTO gradients, tolerance stop).
+Three of them (2D and 3D) are also run step by step with every iteration
+checked against the oracle stepping from the GPU's labels (particle sets
+exact, gradients within 1e-5, labels outside the decision margin, the AUTO
+switch and stop where the oracle's rule puts them), and the served result
+must equal that checked run bit for bit.
 """
 import numpy as np
 import pytest
@@ -16,6 +20,7 @@ pytestmark = pytest.mark.gpu
 from paper_1403_0240_amd import sobrc as S  # noqa: E402
 from paper_1403_0240_amd import serve as SV  # noqa: E402
 from paper_1403_0240_amd import workloads as W  # noqa: E402
+from shadow import Shadow  # noqa: E402
 
 TOL, MAX_IT = 1e-3, 120
 
@@ -70,6 +75,64 @@ def test_each_result_same_alone_and_in_mix(realtime):
         assert r.latency > 0
     stats = SV.latency_stats(done)
     assert stats["p99_s"] >= stats["p50_s"] > 0
+    assert all(r.error is None for r in done)
+
+
+def test_served_results_match_oracle(ora):
+    """Requests 0 and 1 (2D) and 2 (3D): the served labels and iteration
+    counts equal a stand-alone run checked against the oracle at every
+    iteration."""
+    reqs = requests()
+    srv = SV.Server(hbm_budget=1 << 32, slots=4, tol=TOL, max_iters=MAX_IT, tick=3)
+    done = {r.rid: r for r in srv.serve(reqs, realtime=False)}
+    srv.close()
+    for rid in (0, 1, 2):
+        w = reqs[rid][1]
+        print(f"[serve request {rid} ndim={w.ndim} shape={w.image.shape} shadowed]", flush=True)
+        ctx, img, lab = S.from_workload(w, max_particles=SV.default_capacity(w))
+        S.init_labels(ctx, img, lab)
+        sh = Shadow(ora, w, ctx, S.MODE_AUTO, tol=TOL).run(MAX_IT)
+        sh.report(f"request {rid}")
+        assert sh.checked == sh.steps
+        r = done[rid]
+        assert r.iterations == sh.steps
+        assert r.switch_iter == sh.rule.switch_iter
+        assert np.array_equal(r.labels, sh.L)
+
+
+def test_failed_request_leaves_the_others_intact():
+    """A request whose particle set outgrows its capacity fails on its own:
+    it retires with the error and the labels of its last committed
+    iteration (those of its stand-alone run, which reports the same error),
+    while every other request ends exactly as alone."""
+    reqs = requests()[:5]
+    w1 = reqs[1][1]
+    ctx, img, lab = S.from_workload(w1, max_particles=SV.default_capacity(w1))
+    S.init_labels(ctx, img, lab)
+    cap1 = S.particle_count(ctx) + 8  # room for the initial contour only
+    items = [(t, w, cap1) if k == 1 else (t, w) for k, (t, w) in enumerate(reqs)]
+    print(f"[serve failing request capacity={cap1}]", flush=True)
+    ctx, img, lab = S.from_workload(w1, max_particles=cap1)
+    S.init_labels(ctx, img, lab)
+    with pytest.raises(S.SobrcError) as e:
+        S.run(ctx, MAX_IT, TOL, S.MODE_AUTO)
+    assert e.value.code == S.ECAPACITY
+    fail_labels = S.get_labels(ctx).cpu().numpy()
+    fail_iters = len(S.get_history(ctx)[0])
+    srv = SV.Server(hbm_budget=1 << 32, slots=2, tol=TOL, max_iters=MAX_IT, tick=3)
+    done = {r.rid: r for r in srv.serve(items, realtime=False)}
+    srv.close()
+    assert sorted(done) == list(range(len(items)))
+    r = done[1]
+    assert r.error is not None and str(S.ECAPACITY) in r.error
+    assert r.iterations == fail_iters
+    assert np.array_equal(r.labels, fail_labels)
+    for k, (_, w) in enumerate(reqs):
+        if k == 1:
+            continue
+        L, t, sw = standalone(w)
+        assert done[k].error is None
+        assert done[k].iterations == t and np.array_equal(done[k].labels, L)
 
 
 def test_unbatchable_requests_are_refused():

@@ -24,6 +24,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1403_0240_amd import sobrc as S  # noqa: E402
 from paper_1403_0240_amd import workloads as W  # noqa: E402
+from shadow import Shadow  # noqa: E402
 from topo_invariants import topo  # noqa: E402
 
 MARGIN = 1e-4
@@ -169,34 +170,32 @@ RUNS = {
 }
 
 
+def topo_shadow_marginal(w):
+    """Label comparison of a shadowed step with ranked acceptance: differing
+    pixels must all be marginal in the ranked sense (topo_marginal)."""
+    def cmp(info, g, L_g, L_o):
+        diff = L_g != L_o
+        if diff.any():
+            marg = topo_marginal(w.labels.shape, info["lin"], g, MARGIN * np.abs(g).max())
+            bad = np.flatnonzero(diff & ~marg)
+            assert len(bad) == 0, f"{len(bad)} non-marginal pixels differ"
+        return int(diff.sum())
+    return cmp
+
+
 @pytest.mark.parametrize("mode", ["sobolev", "l2"])
 @pytest.mark.parametrize("name", sorted(RUNS))
 def test_controlled_trajectory(ora, name, mode):
-    """Independent GPU and oracle trajectories with topological control agree
-    after every step until the first marginal decision."""
+    """Ten iterations with topological control, each checked against the
+    oracle stepping from the GPU's labels: particle set, gradients, labels
+    outside the ranked margin, flips, reversals and statistics."""
     w = _with_topo(RUNS[name]())
-    m_o = ora.MODE_SOBOLEV if mode == "sobolev" else ora.MODE_L2
     m_g = S.MODE_SOBOLEV if mode == "sobolev" else S.MODE_L2
     print(f"[case {name} {mode} topo]", flush=True)
-    P = ora.params_of(w)
     ctx, img, lab = gpu_state(w, cap=max(4096, 2 * w.labels.size))
-    L_o = w.labels.copy()
-    nfl = torch.zeros(1, dtype=torch.int32, device="cuda")
-    for t in range(10):
-        L_next, info = ora.step(P, w.image, L_o, m_o)
-        S.step(ctx, m_g, nfl)
-        L_g = S.get_labels(ctx).cpu().numpy()
-        diff = L_g != L_next
-        if diff.any():
-            g = info["dE_h1"] if mode == "sobolev" else info["dE_l2"]
-            thr = MARGIN * np.abs(g).max()
-            marg = topo_marginal(w.labels.shape, info["lin"], g, thr)
-            bad = np.flatnonzero(diff & ~marg)
-            assert len(bad) == 0, f"step {t}: {len(bad)} non-marginal pixels differ"
-            print(f"  step {t}: {int(diff.sum())} marginal differences; stopping comparison")
-            return
-        assert int(nfl.item()) == info["flips"]
-        L_o = L_next
+    sh = Shadow(ora, w, ctx, m_g, marginal=topo_shadow_marginal(w)).run(10)
+    sh.report(f"{name} {mode} topo")
+    assert sh.checked == 10
 
 
 @pytest.mark.parametrize("name,iters", [("blobs2d_512", 60), ("ellipsoids3d_64_dense", 40)])
@@ -224,19 +223,20 @@ def test_controlled_run_keeps_every_region_intact(name, iters):
 
 
 def test_auto_mode_with_control_matches_oracle(ora):
+    """AUTO mode with ranked, controlled acceptance: every iteration checked
+    against the oracle from the GPU's labels, the switch and the stop where
+    the oracle's AUTO rule puts them; a graph-replayed run from the same start
+    stops there with the same labels."""
     w = _with_topo(W.disk2d())
     print("[case disk2d_128 auto topo]", flush=True)
-    P = ora.params_of(w)
-    o = ora.run_ex(P, w.image, w.labels, ora.MODE_AUTO, 200, 1e-3)
     ctx, img, lab = gpu_state(w, cap=2 * w.labels.size)
-    t_g = S.run(ctx, 200, 1e-3, S.MODE_AUTO)
-    L_g = S.get_labels(ctx).cpu().numpy()
-    gn, gf, gb = S.get_history(ctx, reversals=True)
-    if (L_g != o["L"]).any() or t_g != o["t"]:
-        pytest.skip("trajectories split at a marginal decision")
-    assert np.array_equal(gn, o["n"]) and np.array_equal(gf, o["flips"])
-    assert np.array_equal(gb, o["reversals"])
-    assert S.gradient_switch(ctx) == o["switch"]
+    sh = Shadow(ora, w, ctx, S.MODE_AUTO, tol=1e-3, marginal=topo_shadow_marginal(w)).run(200)
+    sh.report("disk2d_128 auto topo")
+    assert sh.stopped and sh.checked == sh.steps
+    ctx2, _, _ = gpu_state(w, cap=2 * w.labels.size)
+    assert S.run(ctx2, 200, 1e-3, S.MODE_AUTO) == sh.steps
+    assert S.gradient_switch(ctx2) == sh.rule.switch_iter
+    assert np.array_equal(S.get_labels(ctx2).cpu().numpy(), sh.L)
 
 
 def test_capacity_roll_back_with_control():

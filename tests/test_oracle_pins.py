@@ -423,16 +423,46 @@ def test_reversals_count_consecutive_changes(ora, seed):
     assert np.array_equal(stamp.astype(np.int64), last)
 
 
+def _auto_cases():
+    out = []
+    with open(os.path.join(GOLDEN, "auto_rule.txt")) as fh:
+        for line in fh:
+            if not line.strip() or line.startswith("#"):
+                continue
+            head, seq = line.split("|")
+            name, mode, tol, sw, iters = head.split()
+            rows = [tuple(int(v) for v in item.split()) for item in seq.split(";")]
+            out.append((name, int(mode), float(tol), int(sw), int(iters), rows))
+    return out
+
+
+@pytest.mark.parametrize("case", _auto_cases(), ids=lambda c: c[0])
+def test_auto_rule_golden(ora, case):
+    """The AUTO switch and the stop of a run against hand-worked sequences of
+    (N_t, flips, reversals) (golden auto_rule.txt)."""
+    name, mode, tol, sw, iters, rows = case
+    rule = ora.AutoRule(mode, tol)
+    done = 0
+    for n, f, b in rows:
+        expect_grad = ora.MODE_L2 if mode == ora.MODE_L2 or (sw >= 0 and done >= sw) else ora.MODE_SOBOLEV
+        assert rule.grad == expect_grad, f"{name}: gradient of iteration {done}"
+        stop = rule.update(n, f, b)
+        done += 1
+        assert rule.t == done
+        if stop:
+            break
+    assert (rule.switch_iter, done) == (sw, iters), name
+
+
 @pytest.mark.parametrize("case", ["disk", "blobs"])
 def test_auto_mode_is_sobolev_then_l2(ora, case):
-    """AUTO mode, checked step by step with the plain step function: until the
-    switch the iterations are Sobolev iterations, the switch comes at the first
-    pair of consecutive oscillating iterations (counted here from label
-    snapshots), from then on the iterations are L2 iterations, and the run
-    ends at the tolerance or at the second L2 iteration in a row in which every
-    flip is a reversal.  On the disk the pure Sobolev flow ends in a period-2
-    oscillation (Eq. (6) remark) and never meets the tolerance; AUTO does.  On
-    the noisy blobs the L2 flow ends in a settled cycle of a few pixels."""
+    """AUTO runs compose from plain steps: each iteration is an ora.step with
+    the gradient the AUTO rule (pinned above) names, its flips and reversals
+    are counted here from label snapshots by set algebra, and the run switches
+    and stops where the rule says.  On the disk the pure Sobolev flow ends in
+    a period-2 oscillation (Eq. (6) remark) and never meets the tolerance;
+    AUTO does.  On the noisy blobs the L2 flow ends in a settled cycle of a
+    few pixels."""
     w = W.disk2d() if case == "disk" else W.blobs2d(12, side_lo=256, side_hi=400, square=True)
     P = ora.params_of(w)
     I = w.image.astype(np.float64)
@@ -443,30 +473,24 @@ def test_auto_mode_is_sobolev_then_l2(ora, case):
     auto = ora.run_ex(P, I, w.labels, ora.MODE_AUTO, cap, tol)
     s = auto["switch"]
     assert 0 < s < auto["t"] < cap
+    rule = ora.AutoRule(ora.MODE_AUTO, tol)
     L = w.labels.copy()
     prev_changed = np.zeros(L.size, bool)
-    osc_prev = cyc_prev = False
-    expect_switch, expect_stop, why = None, None, None
-    t = 0
-    while expect_stop is None:
-        mode = ora.MODE_SOBOLEV if expect_switch is None or t < expect_switch else ora.MODE_L2
-        L_next, info = ora.step(P, I, L, mode, want_arrays=False)
+    last_cycle = False
+    while True:
+        t = rule.t
+        assert t < cap
+        L_next, info = ora.step(P, I, L, rule.grad, want_arrays=False)
         changed = (L_next != L).reshape(-1)
         f, r = int(changed.sum()), int((changed & prev_changed).sum())
         assert (info["n"], f, r) == (auto["n"][t], auto["flips"][t], auto["reversals"][t])
-        osc, cyc = f > 0 and 2 * r >= f, f > 0 and r == f
-        l2_both = expect_switch is not None and t - 1 >= expect_switch
-        if f < tol * info["n"]:
-            expect_stop, why = t + 1, "tolerance"
-        elif l2_both and cyc and cyc_prev:
-            expect_stop, why = t + 1, "cycle"
-        if expect_switch is None and osc and osc_prev:
-            expect_switch = t + 1
-        osc_prev, cyc_prev, prev_changed, L = osc, cyc, changed, L_next
-        t += 1
-        assert t <= cap
-    assert expect_switch == s and expect_stop == auto["t"]
-    assert why == ("tolerance" if case == "disk" else "cycle")
+        last_cycle = f > 0 and r == f
+        prev_changed, L = changed, L_next
+        if rule.update(info["n"], f, r):
+            break
+    assert rule.switch_iter == s and rule.t == auto["t"]
+    # the disk ends at the tolerance, the blobs in an L2 cycle
+    assert last_cycle == (case == "blobs")
     assert np.array_equal(L, auto["L"])
 
 
