@@ -307,6 +307,21 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n,
                                  const int32_t* d_b, const float* d_in, float* d_out,
                                  void* d_workspace, size_t ws_bytes, void* stream);
 
+/* sobolev_smooth_particles for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation with its scratch memory in a static
+ * device array of SOBRC_STATIC_SCRATCH_BYTES (one per GPU, held until the
+ * process ends); the caller passes only inputs and outputs.  Allocates
+ * nothing.  EINVAL when sobolev_particles_workspace_size(params, n) exceeds
+ * the static size.  Every call on one GPU uses that GPU's one array: calls
+ * that overlap on one GPU (other streams or threads) race and must be
+ * serialised by the caller.  Synchronises once, as sobolev_smooth_particles. */
+#define SOBRC_STATIC_SCRATCH_BYTES (32u << 20)
+int32_t sobolev_smooth_particles_static(const sobrc_params* params, int64_t n,
+                                        const int32_t* d_lin, const int32_t* d_a,
+                                        const int32_t* d_b, const float* d_in, float* d_out,
+                                        void* stream);
+
 /* Kernel timing with HIP events on the launch stream.  profile_enable(ctx, 1)
  * records an event pair around every kernel the context launches;
  * profile_read synchronises and returns, per kernel kind k (see

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1386,9 +1387,16 @@ int32_t sobolev_particles_workspace_size(const sobrc_params* params, int64_t n, 
     return SOBRC_OK;
 }
 
-int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const int32_t* d_lin, const int32_t* d_a,
-                                 const int32_t* d_b, const float* d_in, float* d_out, void* d_ws, size_t ws_bytes,
-                                 void* stream)
+}  // extern "C"
+
+namespace {
+
+// Eq. (6) on caller-given particles with the scratch memory at d_ws
+// (ws_bytes, 256-byte aligned): bins the particles by tile, runs the staged
+// Sobolev kernel, writes d_out in input order.
+int32_t smooth_particles_ws(const sobrc_params* params, int64_t n, const int32_t* d_lin, const int32_t* d_a,
+                            const int32_t* d_b, const float* d_in, float* d_out, void* d_ws, size_t ws_bytes,
+                            void* stream)
 {
     if (!params)
         return fail(SOBRC_EINVAL, "params is NULL");
@@ -1425,9 +1433,10 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const in
     hipStream_t s = (hipStream_t)stream;
     SobW sw{};
     SOBRC_TRY(upload_tables(g, params->E, params->eps, b.W, &sw, s));
-    SOBRC_HIP(hipMemsetAsync(b.ds, 0, sizeof(DevState), s), "hipMemsetAsync");
-    SOBRC_HIP(hipMemsetAsync(b.tcnt, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
-    SOBRC_HIP(hipMemsetAsync(fill, 0, (size_t)g.ntiles * 4, s), "hipMemsetAsync");
+    static_assert(sizeof(DevState) % 4 == 0, "state block in words");
+    SOBRC_HIP(launch_fill_u32((unsigned*)b.ds, 0u, sizeof(DevState) / 4, s), "k_fill_u32");
+    SOBRC_HIP(launch_fill_u32(b.tcnt, 0u, (size_t)g.ntiles, s), "k_fill_u32");
+    SOBRC_HIP(launch_fill_u32(fill, 0u, (size_t)g.ntiles, s), "k_fill_u32");
     SOBRC_HIP(launch_bin_count(g, b, n, d_lin, d_a, d_b, s), "k_bin_count");
     DevState h;
     SOBRC_HIP(hipMemcpyAsync(&h, b.ds, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
@@ -1439,6 +1448,77 @@ int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const in
     SOBRC_HIP(launch_sobolev(g, b, sw, 0, b.dE, b.gH1, 0, 0, s), "k_sobolev");
     SOBRC_HIP(launch_unbin(b, n, origin, b.gH1, d_out, s), "k_unbin");
     return SOBRC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sobolev_smooth_particles(const sobrc_params* params, int64_t n, const int32_t* d_lin, const int32_t* d_a,
+                                 const int32_t* d_b, const float* d_in, float* d_out, void* d_ws, size_t ws_bytes,
+                                 void* stream)
+{
+    return smooth_particles_ws(params, n, d_lin, d_a, d_b, d_in, d_out, d_ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------- stateless update without allocation
+//
+// Scratch memory of sobolev_smooth_particles_static: a file-scope device
+// array, one copy per GPU for the life of the process.  Host code never
+// passes the array's name to a kernel (in host code it is a stand-in, not a
+// device address): each device's address comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+static __device__ __align__(256) char scratch[SOBRC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_address(void** out)
+{
+    int dev = 0;
+    SOBRC_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SOBRC_EDEVICE, "device %d outside the %d devices the scratch table holds", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        SOBRC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (!p)
+            return fail(SOBRC_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SOBRC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sobolev_smooth_particles_static(const sobrc_params* params, int64_t n, const int32_t* d_lin,
+                                        const int32_t* d_a, const int32_t* d_b, const float* d_in, float* d_out,
+                                        void* stream)
+{
+    if (!params)
+        return fail(SOBRC_EINVAL, "params is NULL");
+    size_t need = 0;
+    SOBRC_TRY(sobolev_particles_workspace_size(params, n, &need));
+    if (need > (size_t)SOBRC_STATIC_SCRATCH_BYTES)
+        return fail(SOBRC_EINVAL, "%lld particles on this grid need %zu bytes of scratch > the static %zu bytes",
+                    (long long)n, need, (size_t)SOBRC_STATIC_SCRATCH_BYTES);
+    if (n == 0)
+        return SOBRC_OK;
+    if (!d_lin || !d_a || !d_b || !d_in || !d_out)
+        return fail(SOBRC_EINVAL, "NULL device pointer");
+    void* ws = nullptr;
+    SOBRC_TRY(scratch_address(&ws));
+    return smooth_particles_ws(params, n, d_lin, d_a, d_b, d_in, d_out, ws, (size_t)SOBRC_STATIC_SCRATCH_BYTES,
+                               stream);
 }
 
 // ------------------------------------------------------------------ profiling

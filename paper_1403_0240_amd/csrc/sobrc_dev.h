@@ -250,6 +250,8 @@ hipError_t launch_unpack(const Geom& g, const Bufs& b, int cur, int32_t* lin, in
                          int32_t* bb, hipStream_t s);
 hipError_t launch_labels_out(const Geom& g, const Bufs& b, int32_t* out, hipStream_t s);
 
+hipError_t launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s);
+
 // Stateless binning for sobolev_smooth_particles.
 hipError_t launch_bin_count(const Geom& g, const Bufs& b, long long n, const int32_t* lin,
                             const int32_t* a, const int32_t* bb, hipStream_t s);

@@ -2616,6 +2616,25 @@ hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur,
     return hipGetLastError();
 }
 
+// Word fill (clears of scratch memory by a kernel, which stream capture
+// records as an ordinary kernel node).
+__global__ __launch_bounds__(kBlock) void k_fill_u32(unsigned* __restrict__ p, unsigned v, unsigned long long n)
+{
+    for (unsigned long long i = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    size_t blocks = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(kBlock), 0, s, p, v,
+                       (unsigned long long)n);
+    return hipGetLastError();
+}
+
 hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* in, float* out,
                           int gated, int use_slots, hipStream_t s)
 {

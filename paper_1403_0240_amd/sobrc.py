@@ -27,7 +27,7 @@ KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write
 EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "compute_l2_diff",
            "sobolev_smooth", "step", "step_with_gradient", "run", "ctx_sync", "get_particles", "get_labels",
            "get_region_stats", "get_history", "get_gradient_mode", "sobolev_particles_workspace_size",
-           "sobolev_smooth_particles", "profile_enable", "profile_read", "batch_workspace_size",
+           "sobolev_smooth_particles", "sobolev_smooth_particles_static", "profile_enable", "profile_read", "batch_workspace_size",
            "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_run",
            "batch_launch_iters", "batch_collect", "batch_set_shape", "batch_autotune", "last_error")
 
@@ -78,6 +78,7 @@ def lib():
         "get_gradient_mode": [V, P(I32), V],
         "sobolev_particles_workspace_size": [P(Params), I64, P(C.c_size_t)],
         "sobolev_smooth_particles": [P(Params), I64, V, V, V, V, V, V, C.c_size_t, V],
+        "sobolev_smooth_particles_static": [P(Params), I64, V, V, V, V, V, V],
         "profile_enable": [V, I32],
         "profile_read": [V, V, V, I32],
         "batch_workspace_size": [I32, P(C.c_size_t)],
@@ -305,6 +306,15 @@ def sobolev_smooth_particles(params: Params, lin, a, b, inp, out=None, stream=No
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=lin.device)
     _check(lib().sobolev_smooth_particles(C.byref(params), n, _ptr(lin), _ptr(a), _ptr(b),
                                           _ptr(inp), _ptr(out), _ptr(ws), nb.value, _stream(stream)))
+    return out
+
+
+def sobolev_smooth_particles_static(params: Params, lin, a, b, inp, out, stream=None):
+    """sobolev_smooth_particles with the library's static scratch memory:
+    allocates nothing (the caller provides the output)."""
+    n = int(lin.numel())
+    _check(lib().sobolev_smooth_particles_static(C.byref(params), n, _ptr(lin), _ptr(a), _ptr(b),
+                                                 _ptr(inp), _ptr(out), _stream(stream)))
     return out
 
 

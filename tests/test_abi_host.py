@@ -128,6 +128,24 @@ def test_stateless_validation(L):
     assert L.sobolev_smooth_particles(C.byref(p), 10, fake, fake, fake, fake, fake, fake, 16, None) == S.EINVAL
 
 
+def test_static_scratch_validation(L):
+    """The no-allocation stateless entry point checks its arguments and its
+    scratch limit on the host, before any device call."""
+    p = _p()
+    fake = C.c_void_p(1 << 20)
+    sp = L.sobolev_smooth_particles_static
+    assert sp(C.byref(p), 0, None, None, None, None, None, None) == S.OK  # nothing to do
+    assert sp(None, 10, fake, fake, fake, fake, fake, None) == S.EINVAL
+    assert sp(C.byref(p), -1, fake, fake, fake, fake, fake, None) == S.EINVAL
+    assert sp(C.byref(p), 10, None, fake, fake, fake, fake, None) == S.EINVAL
+    # more particles than the static scratch holds
+    n = C.c_size_t(0)
+    big = 4 << 20
+    assert L.sobolev_particles_workspace_size(C.byref(p), big, C.byref(n)) == S.OK and n.value > 32 << 20
+    assert sp(C.byref(p), big, fake, fake, fake, fake, fake, None) == S.EINVAL
+    assert b"static" in L.last_error()
+
+
 def test_batch_validation(L):
     """Batch entry points reject bad arguments on the host."""
     nb = C.c_size_t(0)
