@@ -112,13 +112,18 @@ typedef struct {
 
 typedef struct sobrc_ctx sobrc_ctx;
 
-/* Bytes of device workspace a context with these parameters needs.
- * Host only, no device call.  EINVAL on bad parameters. */
+/* Bytes of device workspace a context with these parameters needs: the
+ * label field, two particle-record buffers of max_particles entries (the
+ * contour particles of Fig. 1 at iterations t and t + 1), both gradients,
+ * the per-tile cell lists (text after Eq. (6)), the region statistics of the
+ * photometric estimate (Methods) and the model's extra fields.  Host only,
+ * no device call.  EINVAL on bad parameters. */
 int32_t workspace_size(const sobrc_params* params, size_t* bytes);
 
-/* Create a context inside a caller-owned device workspace (d_workspace,
- * 256-byte aligned, at least workspace_size bytes).  Host only: no device call
- * is made until init_labels.  *out receives a library-owned host handle. */
+/* Create a context -- one segmentation job of the energy of Eq. (10) on one
+ * image -- inside a caller-owned device workspace (d_workspace, 256-byte
+ * aligned, at least workspace_size bytes).  Host only: no device call is made
+ * until init_labels.  *out receives a library-owned host handle. */
 int32_t ctx_create(const sobrc_params* params, void* d_workspace, size_t bytes,
                    sobrc_ctx** out);
 
@@ -154,10 +159,12 @@ int32_t compute_l2_diff(sobrc_ctx* ctx, float* d_dE_l2, void* stream);
  * accumulation).  Asynchronous. */
 int32_t sobolev_smooth(sobrc_ctx* ctx, const float* d_dE_l2, float* d_dE_h1, void* stream);
 
-/* One iteration: L2 gradient, Sobolev update (mode SOBOLEV; mode AUTO until
- * it has switched) or none (mode L2), acceptance as params.topo says (see
- * SOBRC_TOPO_*), then region statistics and the particle set are brought up
- * to date.
+/* One iteration of the Region Competition optimizer with particle-approximated
+ * Sobolev gradients (Introduction, "The Region Competition (RC) algorithm",
+ * and the text after Eq. (6)): L2 gradient, Sobolev update (mode SOBOLEV;
+ * mode AUTO until it has switched) or none (mode L2), acceptance of the
+ * moves with negative gradient as params.topo says (see SOBRC_TOPO_*), then
+ * region statistics and the particle set are brought up to date.
  * If d_nflips != NULL the number of changed pixels is written there (device
  * int32).  Asynchronous, no host synchronisation.  If the new particle set
  * would exceed max_particles the step is rolled back on the device and the
@@ -178,9 +185,11 @@ int32_t step(sobrc_ctx* ctx, int32_t mode, int32_t* d_nflips, void* stream);
  * Asynchronous; errors as step(). */
 int32_t step_with_gradient(sobrc_ctx* ctx, const float* d_grad, int32_t* d_nflips, void* stream);
 
-/* Up to max_iters iterations; stops after the first iteration t whose flip
- * count is below flip_tol * N_t (N_t = particles at the start of t; flip_tol
- * = 0 runs all iterations).  The stop is decided on the device, so the result
+/* Up to max_iters iterations of step(), the optimizer run to convergence
+ * (the paper counts iterations until the contour stops moving, e.g. Fig. 3
+ * and Fig. 8); stops after the first iteration t whose flip count is below
+ * flip_tol * N_t (N_t = particles at the start of t; flip_tol = 0 runs all
+ * iterations), or in mode AUTO at the settled cycle of get_gradient_mode.  The stop is decided on the device, so the result
  * does not depend on how often the host looks.  Synchronises at the end;
  * *h_iters_done (may be NULL) receives the iterations executed. */
 int32_t run(sobrc_ctx* ctx, int32_t max_iters, double flip_tol, int32_t mode,
