@@ -37,10 +37,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # read once, each output written once; neighbour data reused on chip is not
 # counted).
 #   k_l2diff : record 8 + intensity 2 (u16) + face-label stencil 3.4 + gradient write 4
-#   k_sobolev: record 8 + L2 gradient read 4 + Sobolev gradient write 4
+#              + the same value written to its pixel for the brick kernel 4
+#   k_sobolev: L2 gradient read by pixel 4 + Sobolev gradient write 4 (plus the
+#              tile rows' particle bits, 256 B per non-empty tile: about 2 B
+#              per particle on the 3D workload, not counted here)
 #   k_flip   : record 8 + gradient read 4
 #   k_write  : record write 8 (the particle set of the next iteration)
-KERNEL_OWN_BYTES = {"k_l2diff": 17.4, "k_sobolev": 16.0, "k_flip": 12.0, "k_write": 8.0}
+KERNEL_OWN_BYTES = {"k_l2diff": 21.4, "k_sobolev": 8.0, "k_flip": 12.0, "k_write": 8.0}
 
 
 

@@ -192,8 +192,9 @@ void kernel_table(double E, double eps, int T, float* W)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t lab, fstamp, dcnt, dlist, dflat, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, st_n, st_s1, lstat, W, hist,
+    size_t lab, fstamp, dcnt, dlist, dflat, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, dv, st_n, st_s1, lstat, W, hist,
         part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, tstate, tmark, tlist0, tlist1, pmap, du, dt0, dt1, dC, dN, dw, dtheta, dpart, ds;
+    size_t dv_bytes;
     size_t total;
 };
 
@@ -223,6 +224,9 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
     L.tslot = take((size_t)g.ntiles * kSlotWords * 4);
     L.dE = take((size_t)cap * 4);
     L.gH1 = take((size_t)cap * 4);
+    // brick kernels: the L2 gradient scattered to its pixel, whole tiles
+    L.dv_bytes = g.brick ? (size_t)g.ntiles * ((size_t)1 << (g.tsx + g.tsy + g.tsz)) * 4 : 0;
+    L.dv = take(L.dv_bytes);
     L.st_n = take((size_t)p->max_labels * 8);
     L.st_s1 = take((size_t)p->max_labels * 8);
     L.lstat = take((size_t)p->max_labels * 16);
@@ -274,6 +278,7 @@ Bufs carve(const Layout& L, char* base, long long cap)
     b.tslot = (unsigned*)(base + L.tslot);
     b.dE = (float*)(base + L.dE);
     b.gH1 = (float*)(base + L.gH1);
+    b.dv = L.dv_bytes ? (float*)(base + L.dv) : nullptr;
     b.st_n = (long long*)(base + L.st_n);
     b.st_s1 = (long long*)(base + L.st_s1);
     b.lstat = (float4*)(base + L.lstat);
@@ -691,6 +696,8 @@ int32_t sobolev_smooth(sobrc_ctx* c, const float* d_in, float* d_out, void* stre
     if (c->seen_err & kErrCapacity)
         return fail(SOBRC_ECAPACITY, "a step overflowed the particle capacity: init_labels first");
     hipStream_t s = (hipStream_t)stream;
+    // the brick kernels read the L2 gradients by pixel
+    SOBRC_HIP(launch_dense_put(c->g, c->b, c->cur, d_in, s), "k_dense_put");
     return timed(c, SOBRC_K_SOBOLEV, s, "k_sobolev",
                  [&] { return launch_sobolev(c->g, c->b, c->sw, c->cur, d_in, d_out, 0, 1, s); });
 }

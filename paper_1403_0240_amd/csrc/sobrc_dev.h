@@ -21,8 +21,9 @@ constexpr int kPsLdsMax = 64 * 1024;  // LDS bound of the tile-staged PS L2 grad
 // Emission slot of a tile (written by the particle count when the tile is
 // dirty, valid until it is dirty again): word 0 = lo | hi << 16 of a
 // two-label box (0xFFFF: several labels); words 1..64: per tile row
-// (ly + TY*lz), particle bits | bits of pixels labelled lo << 16; words
-// 65..128: particles in the rows before (the row's offset in the tile).
+// (ly + TY*lz), particle bits | bits of pixels labelled lo << 16 (zero for a
+// tile whose box holds one label); words 65..128: particles in the rows
+// before (the row's offset in the tile).
 constexpr int kSlotRows = 64;
 constexpr int kSlotWords = 1 + 2 * kSlotRows;
 constexpr int kBrickMaxH3 = 4;
@@ -157,6 +158,8 @@ struct Bufs {
     unsigned* tslot;         // per tile: emission bitmasks from k_count for k_write
     float* dE;               // L2 gradient, capacity
     float* gH1;              // Sobolev gradient, capacity
+    float* dv;               // brick kernels: L2 gradient per pixel, tile-major (ntiles x tile pixels;
+                             // meaningful at the particles of the current set only)
     long long* st_n;         // region pixel counts, max_labels
     long long* st_s1;        // region intensity sums (fixed point), max_labels
     float4* lstat;           // per label: mean, n/(n-1) (0 if n <= 1), n/(n+1)
@@ -226,6 +229,8 @@ hipError_t launch_init_labels(const Geom& g, const Bufs& b, const int32_t* label
 hipError_t launch_stats_init(const Geom& g, const Bufs& b, const void* img, hipStream_t s);
 hipError_t launch_l2diff(const Geom& g, const Bufs& b, const void* img, int cur, float* out,
                          int gated, hipStream_t s);
+// L2 gradients given in record order to the per-pixel field of the brick kernels.
+hipError_t launch_dense_put(const Geom& g, const Bufs& b, int cur, const float* in, hipStream_t s);
 hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* in,
                           float* out, int gated, int use_slots, hipStream_t s);
 hipError_t launch_flip(const Geom& g, const Bufs& b, const void* img, int cur, const float* grad,

@@ -56,6 +56,17 @@ __device__ __forceinline__ long long lin_of(const Geom& g, int x, int y, int z)
     return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 }
 
+// Pixel (x, y, z) in a tile-major per-pixel field: the tile's pixels are
+// contiguous (x fastest), tiles in tile order.
+__device__ __forceinline__ size_t tile_major(const Geom& g, int x, int y, int z)
+{
+    const unsigned t = (unsigned)(x >> g.tsx) +
+                       (unsigned)g.ntx * ((unsigned)(y >> g.tsy) + (unsigned)g.nty * (unsigned)(z >> g.tsz));
+    const unsigned l = (unsigned)(x & ((1 << g.tsx) - 1)) | ((unsigned)(y & ((1 << g.tsy) - 1)) << g.tsx) |
+                       ((unsigned)(z & ((1 << g.tsz) - 1)) << (g.tsx + g.tsy));
+    return ((size_t)t << (g.tsx + g.tsy + g.tsz)) | l;
+}
+
 __device__ __forceinline__ float img_at(const Geom& g, const void* img, long long i)
 {
     return g.img_u16 ? (float)((const unsigned short*)img)[i] : ((const float*)img)[i];
@@ -473,8 +484,11 @@ __device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restr
         mn = a < mn ? a : mn;
         mx = c > mx ? c : mx;
     }
-    if (mx <= mn)
-        return 0;  // one label: no contour in this tile
+    if (mx <= mn) {  // one label: no contour in this tile
+        if (lane < TY * TZ)
+            slot[1 + lane] = 0u;  // no particle bits (the brick kernels read neighbours' rows unguarded)
+        return 0;
+    }
     bool third = false;
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
@@ -1279,7 +1293,10 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
             float ma = sa / (float)na, mb = sb / (float)nb;
             dext = g.noise ? poisson_move(v, ma, mb) : (v - mb) * (v - mb) - (v - ma) * (v - ma);
         }
-        out[p] = dext + g.lambda * (float)(ca - cb);
+        const float dE = dext + g.lambda * (float)(ca - cb);
+        out[p] = dE;
+        if (b.dv)  // the brick kernels read the values by pixel (a scattered store: not kept in cache)
+            __builtin_nontemporal_store(dE, b.dv + tile_major(g, x, y, z));
     }
 }
 
@@ -1398,8 +1415,23 @@ __device__ __forceinline__ void l2diff_ps_tile_body(const Geom& g, const Bufs& b
                 }
             const float ma = sa / (float)na, mb = sb / (float)nb;
             const float dext = g.noise ? poisson_move(v, ma, mb) : (v - mb) * (v - mb) - (v - ma) * (v - ma);
-            out[p] = dext + g.lambda * (float)(ca - cb);
+            const float dE = dext + g.lambda * (float)(ca - cb);
+            out[p] = dE;
+            if (b.dv)
+                __builtin_nontemporal_store(dE, b.dv + tile_major(g, x, y, z));
         }
+    }
+}
+
+// Given L2 gradients (record order) to their pixels, for the brick kernels.
+__global__ __launch_bounds__(kBlock) void k_dense_put(Geom g, Bufs b, int cur, const float* __restrict__ in)
+{
+    const unsigned n = b.ds->n[cur];
+    const uint2* rec = b.rec[cur];
+    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
+        int x, y, z;
+        unpack(g, rec[p].x, x, y, z);
+        __builtin_nontemporal_store(in[p], b.dv + tile_major(g, x, y, z));
     }
 }
 
@@ -1650,9 +1682,16 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
     // the corner << 17 | side A << 31
     __shared__ unsigned s_core[NCORE];
     __shared__ unsigned s_mode, s_ncore, s_cs;
-    // row tasks per thread: the box spans at most three tiles in x
-    constexpr int RT = (3 * S::BY * S::BZ + kSobBlock - 1) / kSobBlock;
     constexpr int NROWS = S::BY * S::BZ;
+    // One box row per thread.  Its L2 values come from the per-pixel field in
+    // aligned 16-byte chunks: CL chunks left of the tile row, NCH in all, box
+    // x = 0 at element X0 of that window.  Its particle and side bits come
+    // from the slot words of the three tile rows it crosses.
+    constexpr int CL = (H + 3) / 4;
+    constexpr int NCH = CL + (S::TX - 1 + H) / 4 + 1;
+    constexpr int X0 = 4 * CL - H;
+    static_assert(NROWS <= kSobBlock, "one box row per thread");
+    static_assert(S::TX % 4 == 0 && H <= S::TX && S::BX <= 32, "chunks of one tile row, three tile rows per box row");
     static_assert(S::NCELL * 8 + NROWS * 8 <= brick_lds_bytes(ND, H), "brick does not fit its LDS");
     // fields of a core entry: corner cells and rows of the tile's own pixels;
     // the support window of a row fits one 32-bit mask
@@ -1667,7 +1706,10 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
     if ((gated & kAuto) && (ds->lmode & 1u))
         return;  // L2 gradients in force: no smoothing
     const unsigned* ts = b.tstart[cur];
+    const float* __restrict__ dv = b.dv;
     const int lane = lane_id();
+    const int rr = (int)threadIdx.x;  // this thread's box row
+    const int ryi = rr % S::BY, rzi = rr / S::BY;
     for (unsigned ai = a0; ai < a1; ++ai) {
         const unsigned t = b.active[cur][ai];
         const int tx = (int)(t % (unsigned)g.ntx), ty = (int)((t / (unsigned)g.ntx) % (unsigned)g.nty);
@@ -1681,39 +1723,33 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
         const int kz0 = bz0 / S::TZ, nkz = (bz1 - 1) / S::TZ - kz0 + 1;
         // neighbour tiles k = kxi + 3 (kyi + 3 kzi), kxi < nkx, kyi < nky, kzi < nkz
         const int kown = (tx - kx0) + 3 * ((ty - ky0) + 3 * (tz - kz0));
-        const int BYe = by1 - by0, BZe = bz1 - bz0;
         __syncthreads();  // the previous tile is done with LDS
-        // Round trip 1: every load this tile needs except the L2 gradients,
-        // issued together.  Row task ri = (x-tile, box y, box z) follows from
-        // the geometry alone: record range of its tile, the row's particle and
-        // own-side bits and the particles before the row (emission slot).
-        unsigned r_beg[RT], r_end[RT], r_word[RT], r_pre[RT];
-        int r_cell[RT], r_lx0[RT], r_lx1[RT], r_xb[RT], r_row[RT];
+        // One round trip: the box row's slot words and L2 chunks, and (wave 0)
+        // the neighbour tiles' record ranges and label pairs and the tile's
+        // own rows.  A row word of a tile without particles is zero, and the
+        // per-pixel field holds the current L2 value at every particle, so the
+        // row needs nothing else; pixels that are not particles are masked.
+        const int y = oy + ryi, z = oz + rzi;
+        const bool rin = rr < NROWS && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+        const int yc = rin ? y : 0, zc = rin ? z : 0;
+        const unsigned trow = (unsigned)g.ntx * ((unsigned)(yc / S::TY) + (unsigned)g.nty * (unsigned)(zc / S::TZ));
+        const int lrow = (yc % S::TY) + S::TY * (zc % S::TZ);
+        unsigned wd[3];
 #pragma unroll
-        for (int q = 0; q < RT; ++q) {
-            const int ri = (int)threadIdx.x + q * kSobBlock;
-            r_beg[q] = r_end[q] = r_word[q] = r_pre[q] = 0u;
-            r_cell[q] = r_lx0[q] = r_lx1[q] = r_xb[q] = r_row[q] = 0;
-            // ri = kxi + 3 (yi + BY zi): compile-time strides, no division
-            // by the box's runtime extents
-            const int kxi = ri % 3, rest = ri / 3;
-            const int yi = rest % S::BY, zi = rest / S::BY;
-            if (kxi < nkx && yi < BYe && zi < BZe) {
-                const int y = by0 + yi, z = bz0 + zi;
-                const int kx = kx0 + kxi, ky = y / S::TY, kz = z / S::TZ;
-                const unsigned tile = (unsigned)(kx + g.ntx * (ky + g.nty * kz));
-                const int row = (y - ky * S::TY) + S::TY * (z - kz * S::TZ);
-                const unsigned* sl = b.tslot + (size_t)tile * kSlotWords;
-                r_beg[q] = ts[tile];
-                r_end[q] = ts[tile + 1];
-                r_word[q] = sl[1 + row];
-                r_pre[q] = sl[1 + kSlotRows + row];
-                r_lx0[q] = max(bx0 - kx * S::TX, 0);
-                r_lx1[q] = min(bx1 - kx * S::TX, S::TX);
-                r_xb[q] = kx * S::TX - ox;  // box x of the tile row's first pixel (may be < 0)
-                r_row[q] = (y - oy) + S::BY * (z - oz);
-                r_cell[q] = r_xb[q] + S::SX * r_row[q];
-            }
+        for (int k = 0; k < 3; ++k) {
+            const int kx = tx - 1 + k;
+            const bool ok = rin && kx >= 0 && kx < g.ntx;
+            wd[k] = ok ? b.tslot[(size_t)(trow + (unsigned)kx) * kSlotWords + 1 + lrow] : 0u;
+        }
+        float4 ch[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int e = 4 * (c - CL);  // x of the chunk's first pixel, from the tile's
+            const int kxo = e < 0 ? -1 : e / S::TX;
+            const int kx = tx + kxo;
+            const bool ok = rin && kx >= 0 && kx < g.ntx;
+            ch[c] = ok ? *(const float4*)(dv + (size_t)(trow + (unsigned)kx) * NCORE + (e - kxo * S::TX) + S::TX * lrow)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         // wave 0: label pairs of the neighbour tiles (slot headers) and the
         // tile's own rows for the core list
@@ -1733,11 +1769,29 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
                 own_pre = sl[1 + kSlotRows + lane];
             }
         }
-        // meanwhile: clear the brick and the row masks
-        for (int k = threadIdx.x; k < S::NCELL; k += kSobBlock)
-            s_v[k] = make_float2(0.f, 0.f);
-        for (int k = threadIdx.x; k < NROWS; k += kSobBlock)
-            s_m[k] = make_uint2(0u, 0u);
+        if (rr < NROWS) {
+            // particle and lo-side bits of the three tile rows (x from (tx - 1) * TX),
+            // then the box row's window of them
+            const unsigned long long tm = (1ull << S::TX) - 1ull;
+            unsigned long long pw = 0ull, lw = 0ull;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                pw |= ((unsigned long long)wd[k] & tm) << (k * S::TX);
+                lw |= ((unsigned long long)(wd[k] >> 16) & tm) << (k * S::TX);
+            }
+            const unsigned bm = (unsigned)((1ull << S::BX) - 1ull);
+            const unsigned mp = (unsigned)(pw >> (S::TX - H)) & bm, ml = (unsigned)(lw >> (S::TX - H)) & bm;
+            const unsigned mA = mp & ml, mB = mp & ~ml;
+            s_m[rr] = make_uint2(mA, mB);
+            float2* row = s_v + S::SX * rr;
+#pragma unroll
+            for (int i = 0; i < S::BX; ++i) {
+                const int e = X0 + i;
+                const float4 q = ch[e >> 2];
+                const float v = (e & 3) == 0 ? q.x : (e & 3) == 1 ? q.y : (e & 3) == 2 ? q.z : q.w;
+                row[i] = make_float2(((mA >> i) & 1u) ? v : 0.f, ((mB >> i) & 1u) ? v : 0.f);
+            }
+        }
         if (threadIdx.x < 64) {
             // several label pairs around this tile: the staged generic scan
             const unsigned own_hdr = __shfl(hdr, kown);
@@ -1768,41 +1822,6 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
             sob_generic_tile(g, b, cur, in, out, t, lds);
             continue;
         }
-        // Round trip 2: exactly the box's L2 gradients, scattered into the brick
-        float v[RT][S::TX];
-#pragma unroll
-        for (int q = 0; q < RT; ++q) {
-            const unsigned pbits = r_word[q] & 0xffffu;
-            const unsigned xm = ((1u << r_lx1[q]) - 1u) & ~((1u << r_lx0[q]) - 1u);
-            const unsigned bits = r_end[q] > r_beg[q] ? (pbits & xm) : 0u;
-            unsigned idx = r_beg[q] + r_pre[q] + (unsigned)__popc(pbits & ((1u << r_lx0[q]) - 1u));
-#pragma unroll
-            for (int lx = 0; lx < S::TX; ++lx) {
-                v[q][lx] = 0.f;
-                if ((bits >> lx) & 1u)
-                    v[q][lx] = in[idx++];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < RT; ++q) {
-            const unsigned pbits = r_word[q] & 0xffffu, own = r_word[q] >> 16;
-            const unsigned xm = ((1u << r_lx1[q]) - 1u) & ~((1u << r_lx0[q]) - 1u);
-            const unsigned bits = r_end[q] > r_beg[q] ? (pbits & xm) : 0u;
-#pragma unroll
-            for (int lx = 0; lx < S::TX; ++lx) {
-                if ((bits >> lx) & 1u) {
-                    const int c = r_cell[q] + lx;
-                    s_v[c] = ((own >> lx) & 1u) ? make_float2(v[q][lx], 0.f) : make_float2(0.f, v[q][lx]);
-                }
-            }
-            if (bits) {  // this tile row's particles in the box row's side masks
-                const int xb = r_xb[q];
-                const unsigned ma = bits & own, mb = bits & ~own;
-                atomicOr(&s_m[r_row[q]].x, xb >= 0 ? ma << xb : ma >> -xb);
-                atomicOr(&s_m[r_row[q]].y, xb >= 0 ? mb << xb : mb >> -xb);
-            }
-        }
-        __syncthreads();
         const unsigned cs = s_cs, ncore = s_ncore;
         for (unsigned e = threadIdx.x; e < ncore; e += kSobBlock) {
             const unsigned ce = s_core[e];
@@ -2601,6 +2620,14 @@ hipError_t launch_stats_init(const Geom& g, const Bufs& b, const void* img, hipS
 {
     long long nvox = (long long)g.nx * g.ny * g.nz;
     hipLaunchKernelGGL(k_stats_init, dim3(grid_for(nvox, 1024)), dim3(kBlock), 0, s, g, b, img, nvox);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_put(const Geom& g, const Bufs& b, int cur, const float* in, hipStream_t s)
+{
+    if (!b.dv)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_dense_put, dim3(g.gp), dim3(kBlock), 0, s, g, b, cur, in);
     return hipGetLastError();
 }
 
