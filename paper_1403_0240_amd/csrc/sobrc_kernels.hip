@@ -290,6 +290,39 @@ __device__ __forceinline__ unsigned block_sum_u(unsigned v, unsigned* s_red)
 }
 
 // exclusive prefix over the block (thread order); *total receives the sum
+// Block barrier that orders LDS only: global loads already issued stay in
+// flight across it (a full __syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Exclusive block scan whose barriers leave outstanding global loads alone.
+__device__ __forceinline__ unsigned block_exscan_lds(unsigned v, unsigned* s_red, unsigned* total)
+{
+    int lane = lane_id(), w = threadIdx.x >> 6;
+    unsigned inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned t = __shfl_up(inc, o);
+        if (lane >= o)
+            inc += t;
+    }
+    lds_barrier();
+    if (lane == 63)
+        s_red[w] = inc;
+    lds_barrier();
+    unsigned off = 0, tot = 0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+        unsigned c = s_red[i];
+        off += i < w ? c : 0;
+        tot += c;
+    }
+    *total = tot;
+    return off + inc - v;
+}
+
 __device__ __forceinline__ unsigned block_exscan_u(unsigned v, unsigned* s_red, unsigned* total)
 {
     int lane = lane_id(), w = threadIdx.x >> 6;
@@ -830,6 +863,13 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
         n0 = b.st_n[lw];
         q0 = b.st_s1[lw];
     }
+    // many labels: the statistics are final already (atomics in k_flip); a
+    // thread's first label goes out with the other loads
+    long long ln0 = 0, ls0 = 0;
+    if (!g.small_m && tid < g.max_labels) {
+        ln0 = b.st_n[tid];
+        ls0 = b.st_s1[tid];
+    }
     unsigned pre_n = 0, pre_it = 0, pre_lm = 0, pre_sw = 0;
     if (tid == 0 && !is_init) {
         pre_n = ds->n[cur];
@@ -881,9 +921,10 @@ __device__ __forceinline__ void scan_body(const Geom& g, const Bufs& b, int cur,
     }
     if (!g.small_m) {  // statistics already final (atomics in k_flip)
         for (int l = tid; l < g.max_labels; l += kScanThreads) {
-            long long n = b.st_n[l];
+            const long long n = l == tid ? ln0 : b.st_n[l];
+            const long long q = l == tid ? ls0 : b.st_s1[l];
             double d = (double)n;
-            float mu = n > 0 ? (float)((double)b.st_s1[l] * g.fx_inv / d) : 0.f;
+            float mu = n > 0 ? (float)((double)q * g.fx_inv / d) : 0.f;
             float fa = n > 1 ? (float)(d / (d - 1.0)) : 0.f;
             float fb = (float)(d / (d + 1.0));
             b.lstat[l] = make_float4(mu, fa, fb, 0.f);
@@ -1053,6 +1094,12 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     const unsigned tdv = in ? b.dirty[t] : 0u;
     const unsigned tso = in ? b.tstart[cur][t] : 0u;
     const unsigned base = b.part_off[vb.id], abase = b.part_aoff[vb.id];
+    // this wave's first dirty tile of the flat list: its loads are issued
+    // now, so that they overlap the range's work below
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const unsigned item0 = vb.id * (kBlock / 64) + (unsigned)wv;
+    const unsigned nd0 = g.dlistm ? ds->ndirty : 0u;
+    const unsigned tt0 = item0 < nd0 ? b.dflat[item0] : 0u;
     if (ds->undo) {
         // the same gradients k_flip decided on in this step
         const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
@@ -1088,12 +1135,23 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     if (!ds->go)
         return;
     const unsigned epoch = ds->epoch;
+    unsigned ctt0 = 0u, pbase0 = 0u, hdr0 = 0u, word0 = 0u, part0 = 0u;
+    if (item0 < nd0) {
+        ctt0 = b.tcnt[tt0];
+        pbase0 = b.part_off[tt0 >> g.lgRe];
+        const unsigned* slot = b.tslot + (size_t)tt0 * kSlotWords;
+        hdr0 = slot[0];
+        word0 = slot[1 + lane];
+        const int r0 = (int)(tt0 >> g.lgRe) << g.lgRe;
+        for (int k = r0 + lane; k < (int)tt0; k += 64)
+            part0 += b.tcnt[k];
+    }
     // range vb.id: offsets, non-empty tile list, and the clean tiles'
     // records moved unchanged to their new offsets
     const bool dirty = in && (all_dirty || tdv == epoch);
     unsigned tot, totz;
-    const unsigned ex = block_exscan_u(c, s_red, &tot);
-    const unsigned exz = block_exscan_u(c != 0 ? 1u : 0u, s_red, &totz);
+    const unsigned ex = block_exscan_lds(c, s_red, &tot);
+    const unsigned exz = block_exscan_lds(c != 0 ? 1u : 0u, s_red, &totz);
     if (in) {
         b.tstart[nxt][t] = base + ex;
         if (c)
@@ -1107,7 +1165,7 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     s_old[threadIdx.x] = (in && !dirty) ? tso : 0xffffffffu;
     if (threadIdx.x == 0)
         s_ndl = 0;
-    __syncthreads();
+    lds_barrier();
     uint2* rec = b.rec[nxt];
     const uint2* orec = b.rec[cur];
     int j = 0;
@@ -1133,11 +1191,13 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
             if (dst[u] != 0xffffffffu)
                 rec[dst[u]] = r[u];
     }
-    const int wv = threadIdx.x >> 6, lane = lane_id();
     if (g.dlistm) {
-        // dirty tiles from the flat list, round-robin over all waves
-        const unsigned nd = ds->ndirty;
-        for (unsigned item = vb.id * (kBlock / 64) + wv; item < nd; item += vb.n * (kBlock / 64)) {
+        // dirty tiles from the flat list, round-robin over all waves; the
+        // first one's loads went out at the start
+        if (item0 < nd0 && ctt0)
+            wave_write_tile(g, b.lab, tt0, W[wv], hdr0, word0, rec, pbase0 + wave_sum_u(part0));
+        const unsigned nd = nd0;
+        for (unsigned item = item0 + vb.n * (kBlock / 64); item < nd; item += vb.n * (kBlock / 64)) {
             const unsigned tt = b.dflat[item];
             // every load of the tile is issued before any is used
             const unsigned ctt = b.tcnt[tt];
