@@ -2858,17 +2858,23 @@ hipError_t launch_unbin(const Bufs& b, long long n, const unsigned* origin, cons
 // (index, count) that the slot's own launch would have had.  A slot's results
 // are therefore the ones of its stand-alone run, bit for bit.
 
-// Slot holding `item`: the largest i with off[i] <= item (empty slots have
-// off[i] == off[i + 1] and are skipped).
+// Slot holding `item`: the largest i < nslot with off[i] <= item (empty
+// slots have off[i] == off[i + 1] and are skipped; off[0] = 0).  Called with
+// the same item by every lane of a wave: 64 candidates are tested per round
+// with one load each and a ballot, so up to 64 slots take one dependent load
+// (a binary search would take log2(nslot)).
 __device__ __forceinline__ int slot_of(const unsigned* __restrict__ off, int nslot, unsigned item)
 {
-    int lo = 0, hi = nslot;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= item)
-            lo = mid;
-        else
-            hi = mid;
+    const int lane = lane_id();
+    int lo = 0, span = nslot;  // the answer lies in [lo, lo + span) and off[lo] <= item
+    while (span > 1) {
+        const int step = (span + 63) >> 6;
+        const int c = lane * step;
+        const bool ok = c < span && off[lo + c] <= item;
+        const unsigned long long m = __ballot(ok);  // lane 0 always holds
+        const int last = 63 - __clzll((long long)m);
+        lo += last * step;
+        span = min(step, span - last * step);
     }
     return lo;
 }
