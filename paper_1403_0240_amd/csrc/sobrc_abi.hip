@@ -192,7 +192,7 @@ void kernel_table(double E, double eps, int T, float* W)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t lab, fstamp, dcnt, dlist, dflat, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, dv, st_n, st_s1, lstat, W, hist,
+    size_t lab, labt, fstamp, dcnt, dlist, dflat, rec0, rec1, ts0, ts1, act0, act1, tcnt, dirty, tslot, dE, gH1, dv, st_n, st_s1, lstat, W, hist,
         part_f, part_n, part_q, part_cnt, part_act, part_off, part_aoff, tstate, tmark, tlist0, tlist1, pmap, du, dt0, dt1, dC, dN, dw, dtheta, dpart, ds;
     size_t dv_bytes;
     size_t total;
@@ -209,6 +209,7 @@ Layout make_layout(const Geom& g, const sobrc_params* p, long long cap)
         return r;
     };
     L.lab = take((size_t)nvox * 2);
+    L.labt = take((size_t)g.ntiles * ((size_t)1 << (g.tsx + g.tsy + g.tsz)) * 2);
     L.fstamp = take((size_t)nvox * 4);
     L.dcnt = take((size_t)kMaxGrid * 4);  // read as whole 16-byte groups
     L.dlist = take((size_t)g.ge * kBlock * 4);
@@ -263,6 +264,7 @@ Bufs carve(const Layout& L, char* base, long long cap)
 {
     Bufs b{};
     b.lab = (unsigned short*)(base + L.lab);
+    b.labt = (unsigned short*)(base + L.labt);
     b.fstamp = (unsigned*)(base + L.fstamp);
     b.dcnt = (unsigned*)(base + L.dcnt);
     b.dlist = (unsigned*)(base + L.dlist);

@@ -146,6 +146,7 @@ constexpr int kGate = 1, kAuto = 2;
 // Device pointers of one context (all carved from the caller's workspace).
 struct Bufs {
     unsigned short* lab;     // label field, nvox
+    unsigned short* labt;    // the same labels tile-major (ntiles x tile pixels), read by the particle count
     uint2* rec[2];           // particle records {pos, a | b << 16}, capacity each
     unsigned* tstart[2];     // tile_start, ntiles + 1 each
     unsigned* active[2];     // non-empty tiles, ntiles each

@@ -117,6 +117,10 @@ __global__ __launch_bounds__(kBlock) void k_init_labels(Geom g, Bufs b, const in
             l = 0;
         }
         b.lab[i] = (unsigned short)l;
+        {
+            const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
+            b.labt[tile_major(g, x, y, z)] = (unsigned short)l;
+        }
         if (!g.img_u16) {
             unsigned bits = __float_as_uint(((const float*)img)[i]) & 0x7fffffffu;
             mx = bits > mx ? bits : mx;
@@ -442,8 +446,9 @@ __device__ void wave_load_box(const Geom& g, const unsigned short* __restrict__ 
 // labels are enumerated from an LDS copy and marked for a full re-enumeration
 // (slot word 0 = 0xFFFF).
 template <int ND>
-__device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restrict__ lab, unsigned t,
-                                    WaveEmit& W, unsigned* __restrict__ slot)
+__device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restrict__ lab,
+                                    const unsigned short* __restrict__ labt, unsigned t, WaveEmit& W,
+                                    unsigned* __restrict__ slot)
 {
     constexpr int TX = ND == 3 ? 8 : 16, TY = TX, TZ = ND == 3 ? 8 : 1, HZ = ND == 3 ? 1 : 0;
     constexpr int BX = TX + 2, BY = TY + 2, BZ = TZ + 2 * HZ, NROW = BY * BZ;
@@ -454,9 +459,10 @@ __device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restr
     const int tz = (int)(t / ((unsigned)g.ntx * (unsigned)g.nty));
     const int ox = tx * TX - 1, oy = ty * TY - 1, oz = tz * TZ - HZ;
     // every lane issues all of its loads before using any.  With rows of a
-    // multiple of 8 labels (16-byte aligned rows) a box row is read as the
-    // aligned 16-byte chunks of [tx*TX - 8, tx*TX + TX + 8); chunks outside
-    // the row are not read.  Otherwise each label is read on its own.
+    // multiple of 8 labels a box row is read as the aligned 16-byte chunks
+    // of [tx*TX - 8, tx*TX + TX + 8) from the tile-major copy (each a piece
+    // of one tile row: the tile's own rows are one contiguous block); chunks
+    // outside the row are not read.  Otherwise each label is read on its own.
     constexpr int NCH = (TX + 16) / 8;  // 16-byte chunks per box row
     unsigned v[RPL][BX];
     if ((g.nx & 7) == 0) {
@@ -467,13 +473,20 @@ __device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restr
             const int by = r % BY, bz = r / BY;
             const int y = oy + by, z = oz + bz;
             const bool rin = r < NROW && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
-            const uint4* row = (const uint4*)(lab + (rin ? lin_of(g, 0, y, z) : 0));
+            const int yc = rin ? y : 0, zc = rin ? z : 0;
+            // tile row (y, z) of tile column x = 0, in 16-byte units
+            const size_t rbase = (((size_t)g.ntx * ((size_t)(yc >> g.tsy) + (size_t)g.nty * (size_t)(zc >> g.tsz)))
+                                  << (g.tsx + g.tsy + g.tsz)) +
+                                 ((size_t)((yc & (TY - 1)) + TY * (zc & (TZ - 1))) << g.tsx);
+            const uint4* tl = (const uint4*)labt;
             const int c0 = tx * (TX / 8) - 1;  // chunk index of x = tx*TX - 8
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int cc = c0 + c;
                 const bool cin = rin && cc >= 0 && 8 * cc + 8 <= g.nx;
-                ch[i][c] = cin ? row[cc] : make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+                const int x0 = 8 * (cin ? cc : 0);  // first pixel of the chunk
+                const size_t at = (rbase + ((size_t)(x0 >> g.tsx) << (g.tsx + g.tsy + g.tsz)) + (size_t)(x0 & (TX - 1))) >> 3;
+                ch[i][c] = cin ? tl[at] : make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
             }
         }
 #pragma unroll
@@ -726,7 +739,7 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     const int wv = threadIdx.x >> 6;
     for (unsigned i = wv; i < ndl; i += kBlock / 64) {
         const unsigned td = s_dl[i];
-        unsigned cc = wave_count_tile<ND>(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
+        unsigned cc = wave_count_tile<ND>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
             b.tcnt[td] = cc;
             if (cc) {
@@ -796,7 +809,7 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
         }
         const unsigned pos = (unsigned)lo * kBlock + (item - s_pre[lo]);
         const unsigned td = b.dlist[pos];
-        unsigned cc = wave_count_tile<ND>(g, b.lab, td, W[wv], b.tslot + (size_t)td * kSlotWords);
+        unsigned cc = wave_count_tile<ND>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
             b.dflat[item] = td;
             b.tcnt[td] = cc;
@@ -1123,6 +1136,7 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
                 long long lin = lin_of(g, x, y, z);
                 int a = (int)(r.y & 0xffffu);
                 b.lab[lin] = (unsigned short)a;
+                b.labt[tile_major(g, x, y, z)] = (unsigned short)a;
                 long long q = qvalue(g, img, lin);
                 atomicAdd((unsigned long long*)&b.st_n[a], 1ull);
                 atomicAdd((unsigned long long*)&b.st_n[bb], (unsigned long long)(-1ll));
@@ -2015,6 +2029,7 @@ __device__ __forceinline__ void flip_body(const Geom& g, const Bufs& b, const vo
                 lin = (unsigned)lin_of(g, x, y, z);
                 a = (int)(r.y & 0xffffu);
                 b.lab[lin] = (unsigned short)bb;
+                b.labt[tile_major(g, x, y, z)] = (unsigned short)bb;
                 const unsigned st = b.fstamp[lin];
                 rev = st != 0u && st == it;  // this pixel also changed in the previous iteration
                 b.fstamp[lin] = it + 1u;
