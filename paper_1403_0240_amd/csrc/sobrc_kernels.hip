@@ -1299,7 +1299,6 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
         return;
     unsigned n = ds->n[cur];
     const uint2* rec = b.rec[cur];
-    long long nxy = (long long)g.nx * g.ny;
     unsigned p0, p1;
     xcd_chunk(n, vb, p0, p1);
     for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
@@ -1310,19 +1309,27 @@ __device__ __forceinline__ void l2diff_body(const Geom& g, const Bufs& b, const 
         long long i = lin_of(g, x, y, z);
         float v = img_at(g, img, i);
         int ca = 0, cb = 0;
+        {
+            // face neighbours in the tile-major label copy: inside the tile a
+            // fixed offset, across its border the facing pixel of the next tile
+            const long long TX = 1ll << g.tsx, TXY = 1ll << (g.tsx + g.tsy), TV = 1ll << (g.tsx + g.tsy + g.tsz);
+            const int lx = x & ((1 << g.tsx) - 1), ly = y & ((1 << g.tsy) - 1), lz = z & ((1 << g.tsz) - 1);
+            const long long ti = (long long)tile_major(g, x, y, z);
+            const long long sy = (long long)g.ntx * TV, sz = (long long)g.ntx * g.nty * TV;
 #define SOBRC_FACE(cond, j)                    \
     if (cond) {                                \
-        int l = b.lab[j];                      \
+        int l = b.labt[j];                     \
         ca += l == a;                          \
         cb += l == bl;                         \
     }
-        SOBRC_FACE(x > 0, i - 1)
-        SOBRC_FACE(x + 1 < g.nx, i + 1)
-        SOBRC_FACE(y > 0, i - g.nx)
-        SOBRC_FACE(y + 1 < g.ny, i + g.nx)
-        SOBRC_FACE(z > 0, i - nxy)
-        SOBRC_FACE(z + 1 < g.nz, i + nxy)
+            SOBRC_FACE(x > 0, lx > 0 ? ti - 1 : ti - TV + (TX - 1))
+            SOBRC_FACE(x + 1 < g.nx, lx < TX - 1 ? ti + 1 : ti + TV - (TX - 1))
+            SOBRC_FACE(y > 0, ly > 0 ? ti - TX : ti - sy + (TXY - TX))
+            SOBRC_FACE(y + 1 < g.ny, ly < (1 << g.tsy) - 1 ? ti + TX : ti + sy - (TXY - TX))
+            SOBRC_FACE(z > 0, lz > 0 ? ti - TXY : ti - sz + (TV - TXY))
+            SOBRC_FACE(z + 1 < g.nz, lz < (1 << g.tsz) - 1 ? ti + TXY : ti + sz - (TV - TXY))
 #undef SOBRC_FACE
+        }
         float dext;
         if (PSF) {
             // deconvolving model: delta^2 N(x) - 2 delta C(x), theta held fixed
