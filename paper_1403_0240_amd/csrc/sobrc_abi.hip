@@ -141,10 +141,11 @@ Geom make_geom(const sobrc_params* p)
     long long gp = (p->max_particles + kBlock - 1) / kBlock;
     gp = gp < 8 ? gp : (gp + 7) / 8 * 8;  // whole rounds over the 8 XCDs
     g.gp = (int)(gp < 1 ? 1 : (gp > kMaxGrid ? kMaxGrid : gp));
-    // emission ranges of Re = 2^lgRe tiles, at most kMaxGrid ranges unless a
-    // range would exceed kBlock tiles
+    // emission ranges of Re = 2^lgRe tiles, at most kMaxGrid / 2 ranges unless
+    // a range would exceed kBlock tiles (the count and write kernels take one
+    // block per range; 1024 of them are resident at once)
     g.lgRe = 0;
-    while ((1LL << g.lgRe) * kMaxGrid < g.ntiles && (1 << g.lgRe) < kBlock)
+    while ((1LL << g.lgRe) * (kMaxGrid / 2) < g.ntiles && (1 << g.lgRe) < kBlock)
         ++g.lgRe;
     g.Re = 1 << g.lgRe;
     g.ge = (g.ntiles + g.Re - 1) >> g.lgRe;
