@@ -103,7 +103,8 @@ struct Geom {
     int full;                   // T == (h+1)^2: every offset of the brick stencil is inside
     int stage_cap;              // generic-path staging capacity
     int sob_lds;                // dynamic LDS bytes of the generic Sobolev kernel
-    int sob_grid;               // blocks of the Sobolev kernels (multiple of 8)
+    int sob_grid;               // blocks of the generic Sobolev and tile-staged kernels (multiple of 8)
+    int brick_grid;             // blocks of the stand-alone brick Sobolev kernel (multiple of 8)
     int ps_lds;                 // PS model: LDS bytes of the tile-staged L2 gradient (0: per particle)
     int dlistm;                 // dirty tiles go through a flat list balanced over all waves (ge <= kMaxGrid)
     int topo;                   // ranked acceptance with topological control

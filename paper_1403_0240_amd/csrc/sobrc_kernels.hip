@@ -2752,6 +2752,7 @@ hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur,
         hipLaunchKernelGGL(k_sobolev_generic, gd, bd, g.sob_lds, s, g, b, cur, in, out, gated);
         return hipGetLastError();
     }
+    gd = dim3(g.brick_grid);
 #define SOBRC_BRICK(ND, H)                                                                         \
     if (g.ndim == ND && g.h == H) {                                                                \
         if (g.full)                                                                                \
