@@ -208,6 +208,14 @@ int32_t get_particles(sobrc_ctx* ctx, int64_t* h_n, int32_t* d_lin, int32_t* d_a
 /* Copy the current label field to d_labels (int32, nvox).  Asynchronous. */
 int32_t get_labels(sobrc_ctx* ctx, int32_t* d_labels, void* stream);
 
+/* Copy the current label field as the context holds it (uint16, nvox,
+ * x fastest) to `labels`: device memory or page-locked host memory
+ * (hipHostMalloc; pageable host memory makes the copy synchronous).  One
+ * asynchronous copy on `stream`, half the bytes of get_labels: the result
+ * path of a serving loop.  EINVAL for NULL arguments, ESTATE before
+ * init_labels. */
+int32_t get_labels_u16(sobrc_ctx* ctx, uint16_t* labels, void* stream);
+
 /* Region statistics per label (synchronises): pixel count and intensity sum
  * (h_sum may be NULL).  Sums are kept exactly: integers for uint16 images,
  * 2^-s fixed point for fp32 images (s chosen at init_labels from max |I|). */

@@ -826,6 +826,17 @@ int32_t get_labels(sobrc_ctx* c, int32_t* d_labels, void* stream)
     return SOBRC_OK;
 }
 
+int32_t get_labels_u16(sobrc_ctx* c, uint16_t* labels, void* stream)
+{
+    if (!c || !labels)
+        return fail(SOBRC_EINVAL, "ctx and labels must be non-NULL");
+    if (!c->initialized)
+        return fail(SOBRC_ESTATE, "get_labels_u16 before init_labels");
+    const size_t nvox = (size_t)c->g.nx * c->g.ny * c->g.nz;
+    SOBRC_HIP(hipMemcpyAsync(labels, c->b.lab, nvox * 2, hipMemcpyDefault, (hipStream_t)stream), "hipMemcpyAsync");
+    return SOBRC_OK;
+}
+
 int32_t get_region_stats(sobrc_ctx* c, int64_t* h_count, double* h_sum, void* stream)
 {
     if (!c || !h_count)

@@ -3,8 +3,10 @@
 Requests (one image each, with initial labels and method parameters) are
 admitted into the free slots of a batch as soon as a slot and HBM room are
 free, run to convergence together with whatever else is resident, and retire
-on their own: the label field goes back to the host and the slot and memory
-are reused by the next request.  Requests with different kernel geometry
+on their own: the slot is reused at once, and the label field goes back to
+the host (one asynchronous copy into page-locked staging memory, landed in the
+request's array by a helper thread) while the pools run on; the request's
+memory is released when its labels have landed.  Requests with different kernel geometry
 (ndim, E, eps) live in separate batches, one HIP stream each, so their work
 overlaps on the device.
 
@@ -18,7 +20,9 @@ on its own would.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import dataclasses
+import gc
 import time
 
 import numpy as np
@@ -35,7 +39,7 @@ class Request:
     admitted: float = -1.0
     done: float = -1.0
     iterations: int = 0
-    labels: np.ndarray | None = None
+    labels: np.ndarray | None = None  # uint16, the image's shape
     switch_iter: int = -1
     error: str | None = None     # set when the request failed (its labels are those it stopped at)
     footprint: int = 0
@@ -101,6 +105,11 @@ class Server:
         self.used = 0
         self.t0 = time.perf_counter()
         self.admit_stream = torch.cuda.Stream()
+        # retired jobs whose labels are on their way to the host:
+        # (request, job, staging buffer, future of (labels, landing time))
+        self.landing: list[tuple] = []
+        self.staging: dict[int, list] = collections.defaultdict(list)  # power-of-two sizes
+        self.lander = concurrent.futures.ThreadPoolExecutor(max_workers=2)
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -157,22 +166,46 @@ class Server:
                 job.req.admitted = self.now()
 
     # ---------------------------------------------------------------- ticks
+    def _land(self, ev, stage):
+        """Helper thread: wait for the label copy, then move it out of the
+        staging buffer (both release the GIL)."""
+        ev.synchronize()
+        return stage.numpy().copy(), self.now()
+
     def _retire(self, pool: _Pool, k: int, error: str | None = None):
         job = pool.jobs[k]
         req = job.req
         pool.batch.set(k, None, stream=pool.stream)
-        # the label copy-out runs on the pool's stream: allocate, launch and
-        # copy to the host there, so the host copy waits for the kernel
-        with torch.cuda.stream(pool.stream):
-            req.labels = S.get_labels(job.ctx, stream=pool.stream).cpu().numpy()
         req.switch_iter = S.gradient_switch(job.ctx, stream=pool.stream)
         req.iterations = int(pool.iters[k])
         req.error = error
-        req.done = self.now()
         pool.jobs[k] = None
-        self.used -= req.footprint
-        job.ctx.close()
-        self.finished.append(req)
+        shape = tuple(job.ctx.shape)
+        n = int(np.prod(shape))
+        free = self.staging[1 << (n - 1).bit_length()]
+        buf = free.pop() if free else torch.empty(1 << (n - 1).bit_length(), dtype=torch.uint16,
+                                                  pin_memory=True)
+        stage = buf[:n].view(shape)
+        S.get_labels_u16(job.ctx, stage, stream=pool.stream)
+        ev = torch.cuda.Event()
+        ev.record(pool.stream)
+        self.landing.append((req, job, buf, self.lander.submit(self._land, ev, stage)))
+
+    def _landed(self, wait: bool = False):
+        """Finish the retired jobs whose labels have reached the host (with
+        wait, all of them): release their contexts, memory and staging."""
+        keep = []
+        for item in self.landing:
+            req, job, buf, fut = item
+            if not (wait or fut.done()):
+                keep.append(item)
+                continue
+            req.labels, req.done = fut.result()
+            self.staging[buf.numel()].append(buf)
+            self.used -= req.footprint
+            job.ctx.close()
+            self.finished.append(req)
+        self.landing = keep
 
     def step(self) -> bool:
         """One tick: enqueue iterations on every busy pool (one stream each),
@@ -199,29 +232,50 @@ class Server:
                 elif state[k] or it[k] >= self.max_iters:
                     self._retire(pool, k)
         # every pool is idle: place what was prepared, then fill freed slots
+        self._landed()
         self._place()
         self._prepare()
         self._place()
-        return any(p.live() for p in self.pools.values())
+        live = any(p.live() for p in self.pools.values())
+        if not live and self.landing:
+            # nothing runs: the next admission waits for memory that landing frees
+            self._landed(wait=True)
+            self._prepare()
+            self._place()
+            live = any(p.live() for p in self.pools.values())
+        return live
 
     def serve(self, stream_of_requests, realtime: bool = True):
         """Run a list of (arrival seconds, Workload) or (arrival seconds,
         Workload, particle capacity) to completion.  With realtime, each
         request is submitted when the clock reaches its arrival time;
-        otherwise all arrive at time 0 (saturation)."""
+        otherwise all arrive at time 0 (saturation).
+
+        While it runs, the objects the process already holds are frozen out
+        of the garbage collector: a full collection over them (torch's
+        modules and the like) pauses the loop for tens of milliseconds,
+        which would land on whichever request is retiring."""
         pending = collections.deque(
             Request(k, item[1], float(item[0]) if realtime else 0.0,
                     capacity=item[2] if len(item) > 2 else None)
             for k, item in enumerate(stream_of_requests))
-        self.t0 = time.perf_counter()
-        while pending or self.waiting or any(p.live() for p in self.pools.values()):
-            while pending and pending[0].arrival <= self.now():
-                self.submit(pending.popleft())
-            if not self.step() and not self.waiting and pending:
-                time.sleep(max(0.0, min(pending[0].arrival - self.now(), 0.05)))
+        gc.freeze()
+        try:
+            self.t0 = time.perf_counter()
+            while pending or self.waiting or self.landing or any(p.live() for p in self.pools.values()):
+                while pending and pending[0].arrival <= self.now():
+                    self.submit(pending.popleft())
+                if not self.step() and not self.waiting and pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - self.now(), 0.05)))
+            self._landed(wait=True)
+        finally:
+            gc.unfreeze()
         return self.finished
 
     def close(self):
+        self._landed(wait=True)
+        self.lander.shutdown()
+        self.staging.clear()
         for pool in self.pools.values():
             for k, job in pool.live():
                 pool.batch.set(k, None, stream=pool.stream)

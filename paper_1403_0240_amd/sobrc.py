@@ -26,6 +26,7 @@ KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write
 
 EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "compute_l2_diff",
            "sobolev_smooth", "step", "step_with_gradient", "run", "ctx_sync", "get_particles", "get_labels",
+           "get_labels_u16",
            "get_region_stats", "get_history", "get_gradient_mode", "sobolev_particles_workspace_size",
            "sobolev_smooth_particles", "sobolev_smooth_particles_static", "profile_enable", "profile_read", "batch_workspace_size",
            "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_run",
@@ -73,6 +74,7 @@ def lib():
         "ctx_sync": [V, V],
         "get_particles": [V, P(I64), V, V, V, V],
         "get_labels": [V, V, V],
+        "get_labels_u16": [V, V, V],
         "get_region_stats": [V, V, V, V],
         "get_history": [V, I32, V, V, V, P(I32), V],
         "get_gradient_mode": [V, P(I32), V],
@@ -261,6 +263,22 @@ def get_labels(ctx: Context, out=None, stream=None) -> torch.Tensor:
         out = torch.empty(ctx.shape, dtype=torch.int32, device=ctx.device)
     _dev_tensor(out, torch.int32, ctx.shape, "labels")
     _check(lib().get_labels(ctx.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def get_labels_u16(ctx: Context, out=None, stream=None) -> torch.Tensor:
+    """The label field as the context holds it (uint16) in `out`: a device tensor or a
+    page-locked host tensor (one asynchronous copy on `stream`; synchronise before reading
+    a host tensor).  Default: a new device tensor."""
+    if out is None:
+        out = torch.empty(ctx.shape, dtype=torch.uint16, device=ctx.device)
+    ok = (isinstance(out, torch.Tensor) and out.dtype == torch.uint16 and out.is_contiguous()
+          and (out.is_cuda or out.is_pinned()))
+    if not ok:
+        raise ValueError("labels must be a contiguous uint16 tensor on the GPU or in page-locked host memory")
+    if tuple(out.shape) != tuple(ctx.shape):
+        raise ValueError(f"labels has shape {tuple(out.shape)}, expected {tuple(ctx.shape)}")
+    _check(lib().get_labels_u16(ctx.handle, _ptr(out), _stream(stream)))
     return out
 
 

@@ -107,6 +107,8 @@ def test_call_order_and_nulls(L):
         assert L.compute_l2_diff(h, fake, None) == S.ESTATE
         assert L.sobolev_smooth(h, fake, fake, None) == S.ESTATE
         assert L.get_labels(h, fake, None) == S.ESTATE
+        assert L.get_labels_u16(h, fake, None) == S.ESTATE
+        assert L.get_labels_u16(h, None, None) == S.EINVAL
         assert L.get_particles(h, C.byref(C.c_int64()), None, None, None, None) == S.ESTATE
         assert L.ctx_sync(h, None) == S.ESTATE
         assert L.init_labels(h, None, fake, None) == S.EINVAL

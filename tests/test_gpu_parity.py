@@ -214,6 +214,27 @@ def test_stateless_sobolev_particles(ora):
         S.sobolev_smooth_particles(p, bad, z, z + 1, torch.zeros(2, device="cuda"))
 
 
+def test_label_copy_u16():
+    """The uint16 copy-out (device and page-locked host targets) holds the
+    same labels as the int32 one, after iterations have moved the contour."""
+    for w in (W.disk2d(), W.ellipsoids3d(21, n=40, count=3, axes=(4.0, 9.0), margin=11.0)):
+        print(f"[labels u16 ndim={w.ndim} shape={w.image.shape}]", flush=True)
+        ctx, img, lab = S.from_workload(w)
+        S.init_labels(ctx, img, lab)
+        S.run(ctx, 6, 0.0, S.MODE_SOBOLEV)
+        ref = S.get_labels(ctx).cpu().numpy()
+        dev = S.get_labels_u16(ctx)
+        host = torch.empty(ctx.shape, dtype=torch.uint16, pin_memory=True)
+        S.get_labels_u16(ctx, host)
+        torch.cuda.synchronize()
+        assert np.array_equal(dev.cpu().numpy().astype(np.int32), ref)
+        assert np.array_equal(host.numpy().astype(np.int32), ref)
+    with pytest.raises(ValueError):
+        S.get_labels_u16(ctx, torch.empty(ctx.shape, dtype=torch.uint16))  # pageable host memory
+    with pytest.raises(ValueError):
+        S.get_labels_u16(ctx, torch.empty(ctx.shape, dtype=torch.int32, device="cuda"))
+
+
 def test_label_range_error():
     w = W.disk2d()
     w.labels[3, 3] = 7
