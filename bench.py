@@ -155,16 +155,56 @@ def batch_bench(a):
 
     ws = W.batch2d()
     iters = a.steps
-    ctxs = []
+    caps = []
     for w in ws:
         # capacity: three times the initial contour (at least 4096 particles)
         p0 = S.from_workload(w)
         S.init_labels(*p0)
-        cap = max(4096, 3 * S.particle_count(p0[0]))
+        caps.append(max(4096, 3 * S.particle_count(p0[0])))
         del p0
-        ctx, img, lab = S.from_workload(w, max_particles=cap)
-        S.init_labels(ctx, img, lab)
-        ctxs.append((ctx, img, lab))
+
+    def contexts(tile):
+        out = []
+        for w, cap in zip(ws, caps):
+            ctx, img, lab = S.from_workload(w, max_particles=cap, tile=tile)
+            S.init_labels(ctx, img, lab)
+            out.append((ctx, img, lab))
+        return out
+
+    tune = None
+    if a.tile is None:
+        # cell shape for the whole batch (one shape per batch): each shape's
+        # batch timed over a few iterations from the seeded start
+        ms = {}
+        for tile in (S.TILE_DEFAULT, S.TILE_WIDE):
+            cs = contexts(tile)
+            Bt = S.Batch(len(cs))
+            for k, c in enumerate(cs):
+                Bt.set(k, c[0])
+            Bt.autotune(S.MODE_SOBOLEV, iters_per_trial=1)
+            for rep in range(2):  # the first pass warms up (graphs, first launches)
+                for k, c in enumerate(cs):
+                    Bt.set(k, None)
+                    S.init_labels(*c)
+                    Bt.set(k, c[0])
+                if rep == 0:
+                    Bt.run(TUNE_ITERS, 0.0, S.MODE_SOBOLEV)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Bt.run(TUNE_ITERS, 0.0, S.MODE_SOBOLEV)
+            torch.cuda.synchronize()
+            ms[tile] = (time.perf_counter() - t0) * 1e3 / TUNE_ITERS
+            Bt.close()
+            del cs
+        # as the library's autotuner: the default unless the other is 1 % faster
+        tile = S.TILE_WIDE if ms[S.TILE_WIDE] < 0.99 * ms[S.TILE_DEFAULT] else S.TILE_DEFAULT
+        tune = {"chosen": tile_name(2, tile), "iters": TUNE_ITERS,
+                "ms_per_iter": {tile_name(2, k): v for k, v in ms.items()}}
+    else:
+        tile = a.tile
+    for w in ws:
+        w.tile = tile
+    ctxs = contexts(tile)
     n0 = sum(S.particle_count(c[0]) for c in ctxs)
     # stand-alone: each image's run (graph replays), one after another
     for c in ctxs[:2]:
@@ -216,12 +256,14 @@ def batch_bench(a):
         "config": {"workload": "batch2d_64", "images": n,
                    "sides": [int(min(min(w.image.shape) for w in ws)),
                              int(max(max(w.image.shape) for w in ws))],
-                   "E": ws[0].E, "lambda": ws[0].lam, "particles_init": n0},
+                   "E": ws[0].E, "lambda": ws[0].lam, "particles_init": n0,
+                   "tile": tile_name(2, ws[0].tile)},
         "updates_per_s": upd / (batch_ms * 1e-3),
         "standalone": {"images_per_s": n / (solo_ms * 1e-3), "ms_total": solo_ms,
                        "updates_per_s": solo_upd / (solo_ms * 1e-3)},
         "speedup_vs_standalone": solo_ms / batch_ms,
         "launch_shape": {"part_chunk": shape[0], "lg_range": shape[1], "sob_tiles": shape[2]},
+        "tile_autotune": tune,
         "labels_identical_to_standalone": bool(same and upd == solo_upd),
     }
     print(json.dumps(rec), flush=True)
@@ -283,6 +325,9 @@ def parse():
     ap.add_argument("--hbm-gb", type=int, default=16, help="serving workload: HBM budget (GiB)")
     ap.add_argument("--topo", action="store_true",
                     help="ranked acceptance with topological control (simple points)")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="cell shape: 0 default (8^3 / 16^2), 1 wide (16x8x8 / 16x32); "
+                         "default: the faster on this workload (autotuner, before the timed region)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 256 MiB copy used to calibrate byte counters")
     return ap.parse_args()
@@ -300,6 +345,16 @@ def _oracle_rate(w, threads, budget_s, max_iters):
         upd += info["n"]
         done += 1
     return upd, done, time.perf_counter() - t0
+
+
+TUNE_ITERS = 20  # iterations per cell shape in the autotuner's trials
+
+
+def tile_name(ndim, tile):
+    """Cell shape of a context as voxels (x by y (by z))."""
+    if ndim == 3:
+        return "16x8x8" if tile else "8x8x8"
+    return "16x32" if tile else "16x16"
 
 
 def cpu_baseline(w, budget_s):
@@ -347,6 +402,18 @@ def main():
     w = W.make(a.workload)
     if a.topo:
         w.topo = S.TOPO_SIMPLE
+    tune = None
+    if a.tile is not None:
+        w.tile = a.tile
+    else:
+        # cell shape: each admitted shape timed over a few iterations of this
+        # workload from its seeded start (the library's autotuner)
+        img0, lab0 = S.workload_tensors(w)
+        tile, ms = S.tile_autotune(S.workload_params(w), img0, lab0, iters=TUNE_ITERS)
+        del img0, lab0
+        w.tile = tile
+        tune = {"chosen": tile_name(w.ndim, tile), "iters": TUNE_ITERS,
+                "ms_per_iter": {tile_name(w.ndim, k): ms[k] for k in (0, 1) if ms[k] >= 0}}
     ctx, img, lab = S.from_workload(w)
     S.init_labels(ctx, img, lab)
     n0 = S.particle_count(ctx)
@@ -394,11 +461,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "tile_autotune": tune,
         "config": {"workload": w.name, "shape": list(w.image.shape),
                    "image_dtype": str(w.image.dtype), "image_model": "piecewise-constant"
                    if w.model == W.PC else "piecewise-smooth", "E": w.E, "lambda": w.lam,
                    "acceptance": "ranked, topology-controlled" if a.topo else "simultaneous",
-                   "psf_sigma": w.psf_sigma,
+                   "psf_sigma": w.psf_sigma, "tile": tile_name(w.ndim, w.tile),
                    "particles_init": n0, "particles_mean": updates / a.steps,
                    "flips_last": int(hf[-1]) if len(hf) else 0},
     }

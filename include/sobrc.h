@@ -82,6 +82,15 @@ enum { SOBRC_MODE_SOBOLEV = 0, SOBRC_MODE_L2 = 1, SOBRC_MODE_AUTO = 2 };
  * Contexts with SIMPLE take 8 bytes per pixel and 1 per particle more
  * workspace and are not batched. */
 enum { SOBRC_TOPO_OFF = 0, SOBRC_TOPO_SIMPLE = 1 };
+/* Cell lists ("Discrete particle approximation", text after Eq. (6):
+ * particles binned in cells so that the Eq. (6) sums visit only neighbouring
+ * cells; the paper's cells have edge E/2).  Here a cell is a tile of the image, and the results do not
+ * depend on its shape (every sum tests the integer distance), only the
+ * speed: DEFAULT = 8x8x8 voxels in 3D, 16x16 pixels in 2D; WIDE = twice as
+ * long along one axis (16x8x8 in 3D, 16x32 in 2D), so fewer, fuller tiles and
+ * less halo per particle.  tile_autotune times both on a given image.  WIDE
+ * is not available with topological control. */
+enum { SOBRC_TILE_DEFAULT = 0, SOBRC_TILE_WIDE = 1 };
 /* Deconvolving image model (Methods, Eq. (8): J = s_theta(Gamma) * K), used
  * when params.psf_sigma > 0.  K is a separable Gaussian point-spread function:
  * per axis the taps exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma),
@@ -108,6 +117,7 @@ typedef struct {
     int32_t noise;         /* SOBRC_NOISE_GAUSS or SOBRC_NOISE_POISSON */
     int32_t topo;          /* SOBRC_TOPO_OFF or SOBRC_TOPO_SIMPLE (acceptance, see below) */
     double psf_sigma;      /* 0, or the width (pixels, <= 16) of a Gaussian PSF: deconvolving model */
+    int32_t tile;          /* SOBRC_TILE_DEFAULT or SOBRC_TILE_WIDE: shape of the cells (see below) */
 } sobrc_params;
 
 typedef struct sobrc_ctx sobrc_ctx;
@@ -239,6 +249,27 @@ int32_t get_history(sobrc_ctx* ctx, int32_t cap, int32_t* h_n, int32_t* h_flips,
  * L2 gradients and in which every flip was a reversal (a settled period-2
  * cycle: the contour sits in a minimum at pixel resolution). */
 int32_t get_gradient_mode(sobrc_ctx* ctx, int32_t* h_switch_iter, void* stream);
+
+/* Cell-shape autotuner (the cells of the neighbour search, text after
+ * Eq. (6); shapes as SOBRC_TILE_*).  For each shape that params admits
+ * (params->tile is ignored), builds a context inside d_workspace, runs
+ * `iters` iterations (1..1000) of `mode` without a tolerance stop from
+ * d_labels on d_image (int32 labels and the image as for init_labels),
+ * after two warm-up iterations from the same start, and times them with HIP
+ * events on `stream`, in two rounds with the shapes alternating.  h_ms[2]
+ * receives the milliseconds per iteration (the faster round) of
+ * SOBRC_TILE_DEFAULT and SOBRC_TILE_WIDE (-1 for a shape not admitted);
+ * *h_tile is SOBRC_TILE_WIDE if that is at least 1 % faster, else the
+ * default.  Results do not depend on the shape, so a caller then creates its
+ * context with that tile.  d_workspace: device memory of at
+ * least tile_autotune_workspace_size bytes, 256-byte aligned, owned by the
+ * caller; its contents are scratch.  Synchronous.  EINVAL for NULL arguments
+ * or iters out of range; errors of the trial runs (e.g. ECAPACITY) are
+ * returned as they are. */
+int32_t tile_autotune_workspace_size(const sobrc_params* params, size_t* bytes);
+int32_t tile_autotune(const sobrc_params* params, const void* d_image, const int32_t* d_labels, int32_t iters,
+                      int32_t mode, void* d_workspace, size_t bytes, int32_t* h_tile, double* h_ms,
+                      void* stream);
 
 /* ---- batches: many contexts advanced by one set of launches per iteration ----
  *

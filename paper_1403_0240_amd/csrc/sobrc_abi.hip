@@ -79,6 +79,10 @@ int32_t validate(const sobrc_params* p)
     if (p->psf_sigma > 0.0 && (p->model != SOBRC_PC || p->noise != SOBRC_NOISE_GAUSS || p->max_labels > kDeconvM))
         return fail(SOBRC_EINVAL, "the deconvolving model needs SOBRC_PC, SOBRC_NOISE_GAUSS and max_labels <= %d",
                     kDeconvM);
+    if (p->tile != SOBRC_TILE_DEFAULT && p->tile != SOBRC_TILE_WIDE)
+        return fail(SOBRC_EINVAL, "tile must be SOBRC_TILE_DEFAULT or SOBRC_TILE_WIDE (got %d)", p->tile);
+    if (p->tile == SOBRC_TILE_WIDE && p->topo != SOBRC_TOPO_OFF)
+        return fail(SOBRC_EINVAL, "topological control runs on the default tile shape only");
     return SOBRC_OK;
 }
 
@@ -104,13 +108,16 @@ Geom make_geom(const sobrc_params* p)
     g.ny = p->ny;
     g.nz = p->ndim == 3 ? p->nz : 1;
     g.ndim = p->ndim;
+    g.wide = p->tile == SOBRC_TILE_WIDE ? 1 : 0;
     if (p->ndim == 3) {
-        g.tsx = g.tsy = g.tsz = 3;  // 8x8x8 voxel tiles
+        g.tsx = g.wide ? 4 : 3;  // 8x8x8 or 16x8x8 voxel tiles
+        g.tsy = g.tsz = 3;
         g.sy = 10;
         g.sz = 20;
         g.mx = g.my = g.mz = 1023u;
     } else {
-        g.tsx = g.tsy = 4;          // 16x16 pixel tiles
+        g.tsx = 4;                  // 16x16 or 16x32 pixel tiles
+        g.tsy = g.wide ? 5 : 4;
         g.tsz = 0;
         g.sy = 16;
         g.sz = 31;
@@ -161,7 +168,7 @@ Geom make_geom(const sobrc_params* p)
     // by the stateless entry point) takes the same capacity as dynamic LDS.
     g.stage_cap = kStageCap;
     if (g.brick) {
-        int cap = (brick_lds_bytes(g.ndim, g.h) - fixed) / 12 / kSobBlock * kSobBlock;
+        int cap = (brick_lds_bytes(g.ndim, g.h, g.wide) - fixed) / 12 / kSobBlock * kSobBlock;
         g.stage_cap = cap > kStageCap ? kStageCap : cap;
     }
     g.sob_lds = g.stage_cap * 12 + fixed;
@@ -896,6 +903,88 @@ int32_t get_gradient_mode(sobrc_ctx* c, int32_t* h_switch_iter, void* stream)
     return SOBRC_OK;
 }
 
+int32_t tile_autotune_workspace_size(const sobrc_params* params, size_t* bytes)
+{
+    if (!params || !bytes)
+        return fail(SOBRC_EINVAL, "params and bytes must be non-NULL");
+    size_t most = 0;
+    for (int k = SOBRC_TILE_DEFAULT; k <= SOBRC_TILE_WIDE; ++k) {
+        sobrc_params q = *params;
+        q.tile = k;
+        size_t n = 0;
+        if (k == SOBRC_TILE_WIDE && q.topo != SOBRC_TOPO_OFF)
+            continue;  // not admitted: not tried
+        SOBRC_TRY(workspace_size(&q, &n));
+        most = n > most ? n : most;
+    }
+    *bytes = most;
+    return SOBRC_OK;
+}
+
+int32_t tile_autotune(const sobrc_params* params, const void* d_image, const int32_t* d_labels, int32_t iters,
+                      int32_t mode, void* d_workspace, size_t bytes, int32_t* h_tile, double* h_ms, void* stream)
+{
+    if (!params || !d_image || !d_labels || !d_workspace || !h_tile || !h_ms)
+        return fail(SOBRC_EINVAL, "NULL argument");
+    if (iters < 1 || iters > 1000)
+        return fail(SOBRC_EINVAL, "iters must lie in [1, 1000] (got %d)", iters);
+    if (mode != SOBRC_MODE_SOBOLEV && mode != SOBRC_MODE_L2 && mode != SOBRC_MODE_AUTO)
+        return fail(SOBRC_EINVAL, "mode must be SOBRC_MODE_SOBOLEV, SOBRC_MODE_L2 or SOBRC_MODE_AUTO");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SOBRC_HIP(hipEventCreate(&e0), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SOBRC_EDEVICE, "hipEventCreate");
+    }
+    int32_t rc = SOBRC_OK;
+    h_ms[SOBRC_TILE_DEFAULT] = h_ms[SOBRC_TILE_WIDE] = -1.0;
+    // two rounds, shapes alternating; each shape keeps its faster round
+    for (int round = 0; round < 2 && rc == SOBRC_OK; ++round)
+        for (int k = SOBRC_TILE_DEFAULT; k <= SOBRC_TILE_WIDE && rc == SOBRC_OK; ++k) {
+            sobrc_params q = *params;
+            q.tile = k;
+            if (k == SOBRC_TILE_WIDE && q.topo != SOBRC_TOPO_OFF)
+                continue;  // not admitted
+            sobrc_ctx* c = nullptr;
+            rc = ctx_create(&q, d_workspace, bytes, &c);
+            if (rc != SOBRC_OK)
+                break;
+            int32_t done = 0;
+            // warm-up (graph capture), then the timed iterations from the same start
+            rc = init_labels(c, d_image, d_labels, stream);
+            if (rc == SOBRC_OK)
+                rc = run(c, iters < 2 ? iters : 2, 0.0, mode, &done, stream);
+            if (rc == SOBRC_OK)
+                rc = init_labels(c, d_image, d_labels, stream);
+            if (rc == SOBRC_OK && (hipEventRecord(e0, s) != hipSuccess))
+                rc = fail(SOBRC_EDEVICE, "hipEventRecord");
+            if (rc == SOBRC_OK)
+                rc = run(c, iters, 0.0, mode, &done, stream);
+            if (rc == SOBRC_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = fail(SOBRC_EDEVICE, "hipEventRecord");
+            float ms = 0.f;
+            if (rc == SOBRC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = fail(SOBRC_EDEVICE, "hipEventElapsedTime");
+            const int32_t dr = ctx_destroy(c);
+            rc = rc == SOBRC_OK ? dr : rc;
+            if (rc != SOBRC_OK)
+                break;
+            const double per = (double)ms / (double)(done > 0 ? done : 1);
+            h_ms[k] = h_ms[k] < 0.0 || per < h_ms[k] ? per : h_ms[k];
+        }
+    // the default shape unless the other is at least 1 % faster (timing noise
+    // is of that order)
+    int best = SOBRC_TILE_DEFAULT;
+    if (h_ms[SOBRC_TILE_WIDE] >= 0.0 && h_ms[SOBRC_TILE_WIDE] < 0.99 * h_ms[SOBRC_TILE_DEFAULT])
+        best = SOBRC_TILE_WIDE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SOBRC_OK)
+        *h_tile = best;
+    return rc;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches
@@ -1155,8 +1244,8 @@ int32_t batch_set(sobrc_batch* B, int32_t slot, sobrc_ctx* c, void* stream)
             const Geom& a = B->g0;
             const Geom& g = c->g;
             if (a.ndim != g.ndim || a.T != g.T || a.h != g.h || a.brick != g.brick || a.full != g.full ||
-                a.sob_lds != g.sob_lds || memcmp(&B->sw, &c->sw, sizeof(SobW)) != 0)
-                return fail(SOBRC_EINVAL, "batch slots must share ndim, E and eps");
+                a.wide != g.wide || a.sob_lds != g.sob_lds || memcmp(&B->sw, &c->sw, sizeof(SobW)) != 0)
+                return fail(SOBRC_EINVAL, "batch slots must share ndim, E, eps and the tile shape");
         }
     }
     // leaving context: its host parity follows the device

@@ -16,8 +16,16 @@ constexpr int kSmallM = 16;        // label counts up to this use per-block stat
 constexpr int kMaxGrid = 2048;     // blocks of the particle and emission kernels
 constexpr int kPsLdsMax = 64 * 1024;  // LDS bound of the tile-staged PS L2 gradient
 
+// Tile shapes (cells of the particle lists): the default 8x8x8 voxels in 3D
+// and 16x16 pixels in 2D, or the wide shape, twice as long along one axis
+// (16x8x8 in 3D, along x; 16x32 in 2D, along y).  Every shape keeps at most
+// 16 pixels per tile row and at most 64 rows, the emission slot's format.
+__host__ __device__ constexpr int tile_ex(int nd, int wide) { return nd == 3 ? (wide ? 16 : 8) : 16; }
+__host__ __device__ constexpr int tile_ey(int nd, int wide) { return nd == 3 ? 8 : (wide ? 32 : 16); }
+__host__ __device__ constexpr int tile_ez(int nd) { return nd == 3 ? 8 : 1; }
+
 // Largest axis offset h with h*h < T: the halo a Sobolev brick needs.
-// Bricks exist for 3D halos 1..4 (8^3 tiles) and 2D halos 1..8 (16^2 tiles).
+// Bricks exist for 3D halos 1..4 and 2D halos 1..8, for both tile shapes.
 // Emission slot of a tile (written by the particle count when the tile is
 // dirty, valid until it is dirty again): word 0 = lo | hi << 16 of a
 // two-label box (0xFFFF: several labels); words 1..64: per tile row
@@ -32,19 +40,19 @@ constexpr int kBrickMaxH2 = 8;
 // LDS bytes of a brick kernel: the dense brick (two fp32 values per cell) and
 // two side bitmasks per box row or, if larger, the generic path's staging of
 // 256 particles with its weight table.
-__host__ __device__ constexpr int brick_cells(int nd, int h)
+__host__ __device__ constexpr int brick_rows(int nd, int h, int wide)
+{
+    return (tile_ey(nd, wide) + 2 * h) * (nd == 3 ? tile_ez(nd) + 2 * h : 1);
+}
+__host__ __device__ constexpr int brick_cells(int nd, int h, int wide)
 {
     // rows padded to an odd stride (see the brick kernels)
-    return nd == 3 ? ((8 + 2 * h) | 1) * (8 + 2 * h) * (8 + 2 * h) : ((16 + 2 * h) | 1) * (16 + 2 * h);
+    return ((tile_ex(nd, wide) + 2 * h) | 1) * brick_rows(nd, h, wide);
 }
-__host__ __device__ constexpr int brick_rows(int nd, int h)
+__host__ __device__ constexpr int brick_lds_bytes(int nd, int h, int wide)
 {
-    return nd == 3 ? (8 + 2 * h) * (8 + 2 * h) : (16 + 2 * h);
-}
-__host__ __device__ constexpr int brick_lds_bytes(int nd, int h)
-{
-    return brick_cells(nd, h) * 8 + brick_rows(nd, h) * 8 > 256 * 12 + kMaxLim * 4 + 16
-               ? brick_cells(nd, h) * 8 + brick_rows(nd, h) * 8
+    return brick_cells(nd, h, wide) * 8 + brick_rows(nd, h, wide) * 8 > 256 * 12 + kMaxLim * 4 + 16
+               ? brick_cells(nd, h, wide) * 8 + brick_rows(nd, h, wide) * 8
                : 256 * 12 + kMaxLim * 4 + 16;
 }
 
@@ -83,6 +91,7 @@ constexpr int kTopoMaxPasses = 4096;  // passes of the finishing block over the 
 struct Geom {
     int nx, ny, nz, ndim;
     int tsx, tsy, tsz;          // log2 of the tile edge per axis
+    int wide;                   // tile shape: 0 default, 1 wide (tile_ex/ey/ez)
     int ntx, nty, ntz, ntiles;  // tiles per axis, total
     int sy, sz;                 // particle position packing: x | y << sy | z << sz
     unsigned mx, my, mz;        // field masks after shifting

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_init(Geom g, Bufs b, const voi
 // tile plus a one-pixel halo of labels staged in LDS; pixels outside the image
 // hold the sentinel 0xFFFF (labels are < 65535).
 
-constexpr int kBoxMax = 2048;
+constexpr int kBoxMax = 4096;  // bytes of a wave's label box (u16): 18 x 10 x 10 fits
 constexpr unsigned short kNone = 0xFFFF;
 
 struct TileInfo {
@@ -403,33 +403,35 @@ __device__ __forceinline__ unsigned wave_excl_scan_u(unsigned v, unsigned& total
 __device__ void wave_load_box(const Geom& g, const unsigned short* __restrict__ lab, unsigned short* box,
                               const TileInfo& ti)
 {
-    constexpr int kPer = kBoxMax / 2 / 64;  // box entries per lane (box <= 1024)
-    const int nbox = ti.BX * ti.BY * ti.BZ;
+    constexpr int kPer = 16;  // box entries per lane and pass (1024 per pass)
+    const int nbox = ti.BX * ti.BY * ti.BZ;  // <= kBoxMax / 2
     const int ox = ti.tx * ti.TX - 1, oy = ti.ty * ti.TY - 1, oz = ti.tz * ti.TZ - ti.hz;
     const int lane = lane_id();
     // walk the box in (x, y, z) steps of 64 cells without divisions per entry
     int bx = lane % ti.BX, by = (lane / ti.BX) % ti.BY, bz = lane / (ti.BX * ti.BY);
     const int sx = 64 % ti.BX, sy = (64 / ti.BX) % ti.BY, sz = 64 / (ti.BX * ti.BY);
-    unsigned short v[kPer];
+    for (int k0 = 0; k0 < nbox; k0 += 64 * kPer) {
+        unsigned short v[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int k = lane + 64 * u;
-        int x = ox + bx, y = oy + by, z = oz + bz;
-        bool in = k < nbox && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
-        v[u] = in ? lab[lin_of(g, x, y, z)] : kNone;
-        bx += sx;
-        int cy = bx >= ti.BX;
-        bx -= cy ? ti.BX : 0;
-        by += sy + cy;
-        int cz = by >= ti.BY;
-        by -= cz ? ti.BY : 0;
-        bz += sz + cz;
-    }
+        for (int u = 0; u < kPer; ++u) {
+            const int k = k0 + lane + 64 * u;
+            int x = ox + bx, y = oy + by, z = oz + bz;
+            bool in = k < nbox && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+            v[u] = in ? lab[lin_of(g, x, y, z)] : kNone;
+            bx += sx;
+            int cy = bx >= ti.BX;
+            bx -= cy ? ti.BX : 0;
+            by += sy + cy;
+            int cz = by >= ti.BY;
+            by -= cz ? ti.BY : 0;
+            bz += sz + cz;
+        }
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int k = lane + 64 * u;
-        if (k < nbox)
-            box[k] = v[u];
+        for (int u = 0; u < kPer; ++u) {
+            const int k = k0 + lane + 64 * u;
+            if (k < nbox)
+                box[k] = v[u];
+        }
     }
     wave_lds_sync();
 }
@@ -445,12 +447,12 @@ __device__ void wave_load_box(const Geom& g, const unsigned short* __restrict__ 
 // row, so records can be written later without the labels; boxes with more
 // labels are enumerated from an LDS copy and marked for a full re-enumeration
 // (slot word 0 = 0xFFFF).
-template <int ND>
+template <int ND, int WIDE>
 __device__ unsigned wave_count_tile(const Geom& g, const unsigned short* __restrict__ lab,
                                     const unsigned short* __restrict__ labt, unsigned t, WaveEmit& W,
                                     unsigned* __restrict__ slot)
 {
-    constexpr int TX = ND == 3 ? 8 : 16, TY = TX, TZ = ND == 3 ? 8 : 1, HZ = ND == 3 ? 1 : 0;
+    constexpr int TX = tile_ex(ND, WIDE), TY = tile_ey(ND, WIDE), TZ = tile_ez(ND), HZ = ND == 3 ? 1 : 0;
     constexpr int BX = TX + 2, BY = TY + 2, BZ = TZ + 2 * HZ, NROW = BY * BZ;
     constexpr int RPL = (NROW + 63) / 64;  // box rows per lane
     static_assert(BX * BY * BZ <= kBoxMax / 2 && NROW <= 128, "box too large");
@@ -696,7 +698,7 @@ __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned e
 
 // Particle count of every tile of the next state, accumulated per range.
 // Clean tiles keep their previous count.
-template <int ND>
+template <int ND, int WIDE>
 __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, VB vb)
 {
     __shared__ WaveEmit W[kBlock / 64];
@@ -739,7 +741,7 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     const int wv = threadIdx.x >> 6;
     for (unsigned i = wv; i < ndl; i += kBlock / 64) {
         const unsigned td = s_dl[i];
-        unsigned cc = wave_count_tile<ND>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
+        unsigned cc = wave_count_tile<ND, WIDE>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
             b.tcnt[td] = cc;
             if (cc) {
@@ -750,10 +752,10 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     }
 }
 
-template <int ND>
+template <int ND, int WIDE>
 __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int gated, int all_dirty)
 {
-    count_body<ND>(g, b, cur, gated, all_dirty, VB{blockIdx.x, gridDim.x});
+    count_body<ND, WIDE>(g, b, cur, gated, all_dirty, VB{blockIdx.x, gridDim.x});
 }
 
 // Dirty tiles listed by count_body, counted with one wave each: every block
@@ -762,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
 // cluster of dirty tiles in one emission block no longer serialises on its
 // four waves.  The items also go to a flat list (tile ids) for the write
 // kernel.
-template <int ND>
+template <int ND, int WIDE>
 __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, int gated, VB vb)
 {
     __shared__ WaveEmit W[kBlock / 64];
@@ -809,7 +811,7 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
         }
         const unsigned pos = (unsigned)lo * kBlock + (item - s_pre[lo]);
         const unsigned td = b.dlist[pos];
-        unsigned cc = wave_count_tile<ND>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
+        unsigned cc = wave_count_tile<ND, WIDE>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
             b.dflat[item] = td;
             b.tcnt[td] = cc;
@@ -821,10 +823,10 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     }
 }
 
-template <int ND>
+template <int ND, int WIDE>
 __global__ __launch_bounds__(kBlock) void k_count_list(Geom g, Bufs b, int gated)
 {
-    count_list_body<ND>(g, b, gated, VB{blockIdx.x, gridDim.x});
+    count_list_body<ND, WIDE>(g, b, gated, VB{blockIdx.x, gridDim.x});
 }
 
 template <typename T>
@@ -1689,9 +1691,9 @@ __global__ __launch_bounds__(kSobBlock) void k_sobolev_generic(Geom g, Bufs b, i
 
 constexpr int kTapGroup = 16;  // brick reads the stencil keeps in flight
 
-template <int ND, int H>
+template <int ND, int H, int WIDE>
 struct BrickShape {
-    static constexpr int TX = ND == 3 ? 8 : 16, TY = TX, TZ = ND == 3 ? 8 : 1;
+    static constexpr int TX = tile_ex(ND, WIDE), TY = tile_ey(ND, WIDE), TZ = tile_ez(ND);
     static constexpr int HZ = ND == 3 ? H : 0;
     static constexpr int BX = TX + 2 * H, BY = TY + 2 * H, BZ = TZ + 2 * HZ;
     // odd row stride: the rows of a tile then fall on distinct LDS banks
@@ -1728,10 +1730,10 @@ struct TapList {
     int d2[NT];
 };
 
-template <int ND, int H>
-constexpr TapList<BrickShape<ND, H>::NT> make_taps()
+template <int ND, int H, int WIDE>
+constexpr TapList<BrickShape<ND, H, WIDE>::NT> make_taps()
 {
-    using S = BrickShape<ND, H>;
+    using S = BrickShape<ND, H, WIDE>;
     TapList<S::NT> t{};
     int k = 0;
     for (int dz = -S::HZ; dz <= S::HZ; ++dz)
@@ -1750,15 +1752,15 @@ constexpr TapList<BrickShape<ND, H>::NT> make_taps()
 // Tiles active[cur][a0 .. a1) of one context through the brick kernel (the
 // tile loop stays inside this function: the compiler keeps its registers
 // lean that way).
-template <int ND, int H, bool FULL>
+template <int ND, int H, bool FULL, int WIDE>
 __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const SobW& sw, int cur,
                                             const float* __restrict__ in, float* __restrict__ out, int gated,
                                             unsigned a0, unsigned a1)
 {
-    using S = BrickShape<ND, H>;
-    constexpr TapList<S::NT> taps = make_taps<ND, H>();
+    using S = BrickShape<ND, H, WIDE>;
+    constexpr TapList<S::NT> taps = make_taps<ND, H, WIDE>();
     constexpr int NCORE = S::TX * S::TY * S::TZ;
-    __shared__ __align__(16) char lds[brick_lds_bytes(ND, H)];
+    __shared__ __align__(16) char lds[brick_lds_bytes(ND, H, WIDE)];
     // own particles: brick corner cell (12 bits) | x in tile << 12 | box row of
     // the corner << 17 | side A << 31
     __shared__ unsigned s_core[NCORE];
@@ -1773,7 +1775,7 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
     constexpr int X0 = 4 * CL - H;
     static_assert(NROWS <= kSobBlock, "one box row per thread");
     static_assert(S::TX % 4 == 0 && H <= S::TX && S::BX <= 32, "chunks of one tile row, three tile rows per box row");
-    static_assert(S::NCELL * 8 + NROWS * 8 <= brick_lds_bytes(ND, H), "brick does not fit its LDS");
+    static_assert(S::NCELL * 8 + NROWS * 8 <= brick_lds_bytes(ND, H, WIDE), "brick does not fit its LDS");
     // fields of a core entry: corner cells and rows of the tile's own pixels;
     // the support window of a row fits one 32-bit mask
     static_assert((S::TX - 1) + S::SX * ((S::TY - 1) + S::BY * (S::TZ - 1)) < 4096 &&
@@ -1953,22 +1955,22 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
     }
 }
 
-template <int ND, int H, bool FULL>
+template <int ND, int H, bool FULL, int WIDE>
 __device__ __forceinline__ void sobolev_brick_body(const Geom& g, const Bufs& b, const SobW& sw, int cur, const float* __restrict__ in, float* __restrict__ out, int gated, VB vb)
 {
     if (!(gated & kGate) && fill_nan_after_rollback(b, cur, out, vb))
         return;
     unsigned a0, a1;
     xcd_chunk(b.ds->n_active[cur], vb, a0, a1);
-    brick_range<ND, H, FULL>(g, b, sw, cur, in, out, gated, a0, a1);
+    brick_range<ND, H, FULL, WIDE>(g, b, sw, cur, in, out, gated, a0, a1);
 }
 
-template <int ND, int H, bool FULL>
+template <int ND, int H, bool FULL, int WIDE>
 __global__ __launch_bounds__(kSobBlock) void k_sobolev_brick(Geom g, Bufs b, SobW sw, int cur,
                                                             const float* __restrict__ in,
                                                             float* __restrict__ out, int gated)
 {
-    sobolev_brick_body<ND, H, FULL>(g, b, sw, cur, in, out, gated, VB{blockIdx.x, gridDim.x});
+    sobolev_brick_body<ND, H, FULL, WIDE>(g, b, sw, cur, in, out, gated, VB{blockIdx.x, gridDim.x});
 }
 
 // ------------------------------------------------------- acceptance of moves
@@ -2753,18 +2755,20 @@ hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur,
         return hipGetLastError();
     }
     gd = dim3(g.brick_grid);
-#define SOBRC_BRICK(ND, H)                                                                         \
-    if (g.ndim == ND && g.h == H) {                                                                \
+#define SOBRC_BRICK_W(ND, H, WIDE)                                                                 \
+    if (g.ndim == ND && g.h == H && g.wide == WIDE) {                                              \
         if (g.full)                                                                                \
-            hipLaunchKernelGGL((k_sobolev_brick<ND, H, true>), gd, bd, 0, s, g, b, sw, cur, in, out, gated); \
+            hipLaunchKernelGGL((k_sobolev_brick<ND, H, true, WIDE>), gd, bd, 0, s, g, b, sw, cur, in, out, gated); \
         else                                                                                       \
-            hipLaunchKernelGGL((k_sobolev_brick<ND, H, false>), gd, bd, 0, s, g, b, sw, cur, in, out, gated); \
+            hipLaunchKernelGGL((k_sobolev_brick<ND, H, false, WIDE>), gd, bd, 0, s, g, b, sw, cur, in, out, gated); \
         return hipGetLastError();                                                                  \
     }
+#define SOBRC_BRICK(ND, H) SOBRC_BRICK_W(ND, H, 0) SOBRC_BRICK_W(ND, H, 1)
     SOBRC_BRICK(3, 1) SOBRC_BRICK(3, 2) SOBRC_BRICK(3, 3) SOBRC_BRICK(3, 4)
     SOBRC_BRICK(2, 1) SOBRC_BRICK(2, 2) SOBRC_BRICK(2, 3) SOBRC_BRICK(2, 4)
     SOBRC_BRICK(2, 5) SOBRC_BRICK(2, 6) SOBRC_BRICK(2, 7) SOBRC_BRICK(2, 8)
 #undef SOBRC_BRICK
+#undef SOBRC_BRICK_W
     return hipErrorInvalidValue;
 }
 
@@ -2800,17 +2804,16 @@ hipError_t launch_topo(const Geom& g, const Bufs& b, int cur, const float* grad,
 
 hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int all_dirty, hipStream_t s)
 {
-    if (g.ndim == 3)
-        hipLaunchKernelGGL(k_count<3>, dim3(g.ge), dim3(kBlock), 0, s, g, b, cur, gated, all_dirty);
-    else
-        hipLaunchKernelGGL(k_count<2>, dim3(g.ge), dim3(kBlock), 0, s, g, b, cur, gated, all_dirty);
-    if (g.dlistm) {
-        const unsigned gl = g.ge < kListGrid ? (unsigned)g.ge : (unsigned)kListGrid;
-        if (g.ndim == 3)
-            hipLaunchKernelGGL(k_count_list<3>, dim3(gl), dim3(kBlock), 0, s, g, b, gated);
-        else
-            hipLaunchKernelGGL(k_count_list<2>, dim3(gl), dim3(kBlock), 0, s, g, b, gated);
+#define SOBRC_COUNT(ND, WIDE)                                                                              \
+    if (g.ndim == ND && g.wide == WIDE) {                                                                  \
+        hipLaunchKernelGGL((k_count<ND, WIDE>), dim3(g.ge), dim3(kBlock), 0, s, g, b, cur, gated, all_dirty); \
+        if (g.dlistm) {                                                                                    \
+            const unsigned gl = g.ge < kListGrid ? (unsigned)g.ge : (unsigned)kListGrid;                 \
+            hipLaunchKernelGGL((k_count_list<ND, WIDE>), dim3(gl), dim3(kBlock), 0, s, g, b, gated);      \
+        }                                                                                                  \
     }
+    SOBRC_COUNT(3, 0) SOBRC_COUNT(3, 1) SOBRC_COUNT(2, 0) SOBRC_COUNT(2, 1)
+#undef SOBRC_COUNT
     return hipGetLastError();
 }
 
@@ -2951,7 +2954,7 @@ __global__ __launch_bounds__(kSobBlock) void kb_sobolev_generic(const ImgDesc* _
     }
 }
 
-template <int ND, int H, bool FULL>
+template <int ND, int H, bool FULL, int WIDE>
 // The batch's non-empty tiles, numbered through all slots (tpre: the prefix
 // of their counts, written by kb_l2diff), are dealt to the blocks in
 // contiguous runs (XCD-contiguous as in a stand-alone launch): the blocks
@@ -2968,7 +2971,7 @@ __global__ __launch_bounds__(kSobBlock) void kb_sobolev_brick(const ImgDesc* __r
         const int i = slot_of(tpre, nslot, k);  // slot whose run holds tile k (never an empty one)
         const unsigned e = min(a1, tpre[i + 1]);
         const ImgDesc& D = d[i];
-        brick_range<ND, H, FULL>(D.g, D.b, sw, (int)par[i], D.b.dE, D.b.gH1, gated, k - tpre[i], e - tpre[i]);
+        brick_range<ND, H, FULL, WIDE>(D.g, D.b, sw, (int)par[i], D.b.dE, D.b.gH1, gated, k - tpre[i], e - tpre[i]);
         k = e;
     }
 }
@@ -2989,7 +2992,7 @@ __global__ __launch_bounds__(kBlock) void kb_flip(const ImgDesc* __restrict__ d,
     }
 }
 
-template <int ND>
+template <int ND, int WIDE>
 __global__ __launch_bounds__(kBlock) void kb_count(const ImgDesc* __restrict__ d, const unsigned* __restrict__ par,
                                                   const unsigned* __restrict__ offs, int nslot)
 {
@@ -3000,12 +3003,12 @@ __global__ __launch_bounds__(kBlock) void kb_count(const ImgDesc* __restrict__ d
         const ImgDesc& D = d[i];
         const unsigned v = item - off[i];
         if (v < (unsigned)D.g.ge)
-            count_body<ND>(D.g, D.b, (int)par[i], 1, 0, VB{v, (unsigned)D.g.ge});
+            count_body<ND, WIDE>(D.g, D.b, (int)par[i], 1, 0, VB{v, (unsigned)D.g.ge});
         __syncthreads();
     }
 }
 
-template <int ND>
+template <int ND, int WIDE>
 __global__ __launch_bounds__(kBlock) void kb_count_list(const ImgDesc* __restrict__ d,
                                                        const unsigned* __restrict__ offs, int nslot)
 {
@@ -3017,7 +3020,7 @@ __global__ __launch_bounds__(kBlock) void kb_count_list(const ImgDesc* __restric
         const unsigned v = item - off[i];
         const unsigned nb = (unsigned)min(D.g.ge, kBatchListItems);
         if (v < nb && D.g.dlistm)
-            count_list_body<ND>(D.g, D.b, 1, VB{v, nb});
+            count_list_body<ND, WIDE>(D.g, D.b, 1, VB{v, nb});
         __syncthreads();
     }
 }
@@ -3106,20 +3109,22 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
         const dim3 gd = persistent_grid(totals[kPhSob]);
         bool done = false;
         if (g0.brick) {
-#define SOBRC_BRICK(ND, H)                                                                                   \
-    if (!done && g0.ndim == ND && g0.h == H) {                                                                \
+#define SOBRC_BRICK_W(ND, H, WIDE)                                                                          \
+    if (!done && g0.ndim == ND && g0.h == H && g0.wide == WIDE) {                                             \
         if (g0.full)                                                                                          \
-            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, true>), dim3(kPersist), dim3(kSobBlock), 0, s, t.d,  \
-                               t.par, t.tpre, ns, sw, flags);                                                 \
+            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, true, WIDE>), dim3(kPersist), dim3(kSobBlock), 0, s,  \
+                               t.d, t.par, t.tpre, ns, sw, flags);                                            \
         else                                                                                                  \
-            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, false>), dim3(kPersist), dim3(kSobBlock), 0, s, t.d, \
-                               t.par, t.tpre, ns, sw, flags);                                                 \
+            hipLaunchKernelGGL((kb_sobolev_brick<ND, H, false, WIDE>), dim3(kPersist), dim3(kSobBlock), 0, s, \
+                               t.d, t.par, t.tpre, ns, sw, flags);                                            \
         done = true;                                                                                          \
     }
+#define SOBRC_BRICK(ND, H) SOBRC_BRICK_W(ND, H, 0) SOBRC_BRICK_W(ND, H, 1)
             SOBRC_BRICK(3, 1) SOBRC_BRICK(3, 2) SOBRC_BRICK(3, 3) SOBRC_BRICK(3, 4)
             SOBRC_BRICK(2, 1) SOBRC_BRICK(2, 2) SOBRC_BRICK(2, 3) SOBRC_BRICK(2, 4)
             SOBRC_BRICK(2, 5) SOBRC_BRICK(2, 6) SOBRC_BRICK(2, 7) SOBRC_BRICK(2, 8)
 #undef SOBRC_BRICK
+#undef SOBRC_BRICK_W
         }
         if (!done)
             hipLaunchKernelGGL(kb_sobolev_generic, gd, dim3(kSobBlock), g0.sob_lds, s, t.d, t.par, t.off, ns,
@@ -3128,15 +3133,15 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
     hipLaunchKernelGGL(kb_flip, persistent_grid(totals[kPhPart]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
                        flags);
     const unsigned nsc = totals[kPhScan] < 256u ? (totals[kPhScan] ? totals[kPhScan] : 1u) : 256u;
-    if (g0.ndim == 3) {
-        hipLaunchKernelGGL(kb_count<3>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off,
-                           ns);
-        hipLaunchKernelGGL(kb_count_list<3>, persistent_grid(totals[kPhList]), dim3(kBlock), 0, s, t.d, t.off, ns);
-    } else {
-        hipLaunchKernelGGL(kb_count<2>, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off,
-                           ns);
-        hipLaunchKernelGGL(kb_count_list<2>, persistent_grid(totals[kPhList]), dim3(kBlock), 0, s, t.d, t.off, ns);
+#define SOBRC_COUNT(ND, WIDE)                                                                                \
+    if (g0.ndim == ND && g0.wide == WIDE) {                                                                  \
+        hipLaunchKernelGGL((kb_count<ND, WIDE>), persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d,  \
+                           t.par, t.off, ns);                                                                \
+        hipLaunchKernelGGL((kb_count_list<ND, WIDE>), persistent_grid(totals[kPhList]), dim3(kBlock), 0, s,  \
+                           t.d, t.off, ns);                                                                  \
     }
+    SOBRC_COUNT(3, 0) SOBRC_COUNT(3, 1) SOBRC_COUNT(2, 0) SOBRC_COUNT(2, 1)
+#undef SOBRC_COUNT
     hipLaunchKernelGGL(kb_scan, dim3(nsc), dim3(kScanThreads), 0, s, t.d, t.par, t.off, ns, tol, flags);
     hipLaunchKernelGGL(kb_write, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,
                        flags);

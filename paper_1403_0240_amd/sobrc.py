@@ -20,13 +20,14 @@ PC, PS = 0, 1
 NOISE_GAUSS, NOISE_POISSON = 0, 1
 MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 TOPO_OFF, TOPO_SIMPLE = 0, 1
+TILE_DEFAULT, TILE_WIDE = 0, 1
 K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE, K_TOPO, K_DECONV = range(8)
 KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write", "k_topo",
                 "k_deconv")
 
 EXPORTS = ("workspace_size", "ctx_create", "ctx_destroy", "init_labels", "compute_l2_diff",
            "sobolev_smooth", "step", "step_with_gradient", "run", "ctx_sync", "get_particles", "get_labels",
-           "get_labels_u16",
+           "get_labels_u16", "tile_autotune_workspace_size", "tile_autotune",
            "get_region_stats", "get_history", "get_gradient_mode", "sobolev_particles_workspace_size",
            "sobolev_smooth_particles", "sobolev_smooth_particles_static", "profile_enable", "profile_read", "batch_workspace_size",
            "batch_create", "batch_destroy", "batch_set", "batch_step", "batch_run",
@@ -45,7 +46,7 @@ class Params(C.Structure):
         ("image_dtype", C.c_int32), ("model", C.c_int32), ("ps_radius", C.c_int32),
         ("E", C.c_double), ("eps", C.c_double), ("lam", C.c_double),
         ("max_labels", C.c_int32), ("max_particles", C.c_int64), ("noise", C.c_int32),
-        ("topo", C.c_int32), ("psf_sigma", C.c_double),
+        ("topo", C.c_int32), ("psf_sigma", C.c_double), ("tile", C.c_int32),
     ]
 
 
@@ -75,6 +76,8 @@ def lib():
         "get_particles": [V, P(I64), V, V, V, V],
         "get_labels": [V, V, V],
         "get_labels_u16": [V, V, V],
+        "tile_autotune_workspace_size": [P(Params), P(C.c_size_t)],
+        "tile_autotune": [P(Params), V, V, I32, I32, V, C.c_size_t, P(I32), V, V],
         "get_region_stats": [V, V, V, V],
         "get_history": [V, I32, V, V, V, P(I32), V],
         "get_gradient_mode": [V, P(I32), V],
@@ -120,7 +123,8 @@ def _ptr(t):
 
 
 def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.0,
-                max_labels=2, max_particles=1 << 20, noise=0, topo=TOPO_OFF, psf_sigma=0.0) -> Params:
+                max_labels=2, max_particles=1 << 20, noise=0, topo=TOPO_OFF, psf_sigma=0.0,
+                tile=0) -> Params:
     """Parameters for an image of numpy-style shape (ny, nx) or (nz, ny, nx)."""
     if len(shape) == 2:
         ndim, nz, ny, nx = 2, 1, shape[0], shape[1]
@@ -128,7 +132,7 @@ def make_params(shape, image_dtype, E, lam, model=PC, ps_radius=0, eps=1.0 / 24.
         ndim, (nz, ny, nx) = 3, shape
     dt = U16 if image_dtype in (torch.uint16, "uint16", U16) else F32
     return Params(ndim, nx, ny, nz, dt, model, ps_radius, float(E), float(eps), float(lam),
-                  max_labels, int(max_particles), int(noise), int(topo), float(psf_sigma))
+                  max_labels, int(max_particles), int(noise), int(topo), float(psf_sigma), int(tile))
 
 
 def workspace_size(params: Params) -> int:
@@ -282,6 +286,20 @@ def get_labels_u16(ctx: Context, out=None, stream=None) -> torch.Tensor:
     return out
 
 
+def tile_autotune(params: Params, image, labels, iters: int = 4, mode=MODE_SOBOLEV, stream=None):
+    """Time `iters` iterations with each cell shape on this image (device
+    tensors as for init_labels); returns (faster TILE_*, [ms per iteration of
+    TILE_DEFAULT, TILE_WIDE]) (-1 for a shape the parameters do not admit)."""
+    nb = C.c_size_t(0)
+    _check(lib().tile_autotune_workspace_size(C.byref(params), C.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=image.device)
+    tile = C.c_int32(0)
+    ms = (C.c_double * 2)()
+    _check(lib().tile_autotune(C.byref(params), _ptr(image), _ptr(labels), int(iters), mode, _ptr(ws),
+                               nb.value, C.byref(tile), ms, _stream(stream)))
+    return tile.value, [ms[0], ms[1]]
+
+
 def get_region_stats(ctx: Context, stream=None):
     import numpy as np
     M = ctx.params.max_labels
@@ -351,22 +369,34 @@ def profile_read(ctx: Context, reset: bool = True):
     return {KERNEL_NAMES[k]: (float(ms[k]), int(n[k])) for k in range(nk)}
 
 
-def from_workload(w, max_particles=None, device="cuda"):
-    """Context + device tensors for a workloads.Workload; returns (ctx, image, labels)."""
+def workload_params(w, max_particles=None, tile=None) -> Params:
+    """Params of a workloads.Workload (tile None: the workload's own)."""
     import numpy as np
     if max_particles is None:
         max_particles = default_capacity(w.image.shape)
     dt = U16 if w.image.dtype == np.uint16 else F32
-    p = make_params(w.image.shape, dt, w.E, w.lam, w.model, w.ps_radius, w.eps,
-                    w.max_labels, max_particles, getattr(w, "noise", 0), getattr(w, "topo", 0),
-                    getattr(w, "psf_sigma", 0.0))
-    ctx = Context(p, device)
-    if dt == U16:
+    return make_params(w.image.shape, dt, w.E, w.lam, w.model, w.ps_radius, w.eps,
+                       w.max_labels, max_particles, getattr(w, "noise", 0), getattr(w, "topo", 0),
+                       getattr(w, "psf_sigma", 0.0), getattr(w, "tile", 0) if tile is None else tile)
+
+
+def workload_tensors(w, device="cuda"):
+    """The workload's image and initial labels as contiguous device tensors."""
+    import numpy as np
+    if w.image.dtype == np.uint16:
         img = torch.from_numpy(np.ascontiguousarray(w.image, np.uint16)).to(device)
     else:
         img = torch.from_numpy(np.ascontiguousarray(w.image, np.float32)).to(device)
     lab = torch.from_numpy(np.ascontiguousarray(w.labels, np.int32)).to(device)
-    return ctx, img.contiguous(), lab
+    return img.contiguous(), lab.contiguous()
+
+
+def from_workload(w, max_particles=None, device="cuda", tile=None):
+    """Context + device tensors for a workloads.Workload; returns (ctx, image, labels).
+    tile: TILE_DEFAULT / TILE_WIDE (None: the workload's own)."""
+    ctx = Context(workload_params(w, max_particles, tile), device)
+    img, lab = workload_tensors(w, device)
+    return ctx, img, lab
 
 
 def default_capacity(shape) -> int:

@@ -56,6 +56,7 @@ class Workload:
     noise: int = GAUSS
     topo: int = 0              # 1: ranked acceptance with topological control
     psf_sigma: float = 0.0     # > 0: deconvolving model, Gaussian PSF of this width (pixels)
+    tile: int = 0              # cell shape: 0 default, 1 wide (sobrc.TILE_*)
 
     @property
     def ndim(self) -> int:

@@ -237,6 +237,34 @@ def test_launch_shapes_do_not_change_results(dims):
     B.close()
 
 
+@pytest.mark.parametrize("dims", ["2d", "3d"])
+def test_wide_tiles_batch_equals_standalone(dims):
+    """Contexts with wide cells batch like any others (each slot on its
+    stand-alone trajectory), and a batch refuses a context of the other cell
+    shape."""
+    ws = small_2d() if dims == "2d" else small_3d()
+    for w in ws:
+        w.tile = S.TILE_WIDE
+    print(f"[batch wide tiles {dims}]", flush=True)
+    B = S.Batch(len(ws) + 1)
+    ctxs = [make_ctx(w)[0] for w in ws]
+    for k, c in enumerate(ctxs):
+        B.set(k, c)
+    done = B.run(6, 0.0, S.MODE_SOBOLEV)
+    assert (done[: len(ws)] == 6).all()
+    for w, c in zip(ws, ctxs):
+        ref, _, _ = make_ctx(w)
+        assert S.run(ref, 6, 0.0, S.MODE_SOBOLEV) == 6
+        assert_same(snapshot(c), snapshot(ref), "wide cells, batch against stand-alone")
+    w0 = ws[0]
+    w0.tile = S.TILE_DEFAULT
+    other, _, _ = make_ctx(w0)
+    with pytest.raises(S.SobrcError) as e:
+        B.set(len(ws), other)
+    assert e.value.code == S.EINVAL
+    B.close()
+
+
 def test_batch_mixes_likelihoods():
     """Slots with Poisson noise, the piecewise-smooth model or more than 16
     labels (region sums by atomics) run in the same batch as Gaussian

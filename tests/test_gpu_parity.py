@@ -83,6 +83,25 @@ CASES = {
 CAPS = {"many_labels_3d": 16384, "many_labels_3d_u16": 16384}
 
 
+def _wide(make):
+    def w():
+        x = make()
+        x.tile = S.TILE_WIDE
+        return x
+    return w
+
+
+# the same checks with wide cells (16x8x8 voxels, 16x32 pixels): tiles that
+# overhang small images, several wide tiles with ragged tails, multi-label
+# tiles, both PS paths and degenerate extents
+CASES.update({f"{n}_wide": _wide(CASES[n]) for n in [
+    "rand2d_blobs", "rand3d_blobs", "rand3d_u16", "rand2d_ps", "rand3d_ps", "disk2d_128", "half_plane_3d",
+    "many_labels_3d", "ps2d_r8", "ps3d_r4_u16", "thin3d_nz2", "row2d_ny1", "col2d_nx1"]})
+CASES["blobs3d_long_wide"] = _wide(lambda: W.random_multilabel(52, (18, 20, 45), 3, E=6.0, lam=0.5))
+CASES["blobs2d_tall_wide"] = _wide(lambda: W.random_multilabel(53, (75, 41), 3, E=8.0, lam=0.4))
+CAPS["many_labels_3d_wide"] = 16384
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_particles_and_gradients(ora, name):
     w = CASES[name]()
@@ -358,6 +377,59 @@ def test_full_size_first_step(ora, name):
     sh.report(name)
     lin_o, a_o, b_o = ora.particles(sh.P, sh.L)
     match_order(ctx, lin_o, b_o)
+
+
+@pytest.mark.parametrize("name", ["ellipsoids3d_256", "ellipses2d_1024"])
+def test_tile_shapes_agree_full_size(name):
+    """The cell shape only regroups work: from the same start, wide cells give
+    the default cells' particle set and bit-identical L2 and Sobolev gradients
+    on every particle (every sum runs in a fixed order of offsets), and the
+    same labels after each of 8 iterations.  The default cells are checked
+    against the oracle at full size above."""
+    w = W.make(name)
+    print(f"[case {name} tile shapes]", flush=True)
+    out = {}
+    for tile in (S.TILE_DEFAULT, S.TILE_WIDE):
+        w.tile = tile
+        ctx, img, lab = gpu_state(w)
+        lin, a, b = gpu_particles(ctx)
+        key = lin * 65536 + b
+        order = np.argsort(key)
+        dl2 = S.compute_l2_diff(ctx)
+        dh1 = S.sobolev_smooth(ctx, dl2)
+        n = len(lin)
+        labels = []
+        for _ in range(8):
+            S.step(ctx)
+            labels.append(S.get_labels(ctx).cpu().numpy())
+        out[tile] = (key[order], dl2[:n].cpu().numpy()[order], dh1[:n].cpu().numpy()[order], labels)
+        del ctx, img, lab
+    d, wd = out[S.TILE_DEFAULT], out[S.TILE_WIDE]
+    assert np.array_equal(d[0], wd[0]), "particle sets differ"
+    assert np.array_equal(d[1], wd[1]), "L2 gradients differ"
+    assert np.array_equal(d[2], wd[2]), "Sobolev gradients differ"
+    for k, (x, y) in enumerate(zip(d[3], wd[3])):
+        assert np.array_equal(x, y), f"labels differ after iteration {k + 1}"
+
+
+def test_tile_autotune():
+    """The autotuner times both cell shapes on the image and names the faster;
+    a context with its choice runs like any other."""
+    for w in (W.random_multilabel(54, (30, 40, 70), 2, E=6.0, lam=0.5), W.blobs2d(55, side_lo=300, side_hi=300)):
+        print(f"[tile autotune ndim={w.ndim} shape={w.image.shape}]", flush=True)
+        ctx, img, lab = S.from_workload(w)
+        tile, ms = S.tile_autotune(ctx.params, img, lab, iters=3)
+        assert tile in (S.TILE_DEFAULT, S.TILE_WIDE)
+        assert ms[0] > 0 and ms[1] > 0
+        assert tile == (S.TILE_WIDE if ms[1] < 0.99 * ms[0] else S.TILE_DEFAULT)
+        w.tile = tile
+        ctx, img, lab = gpu_state(w)
+        assert S.run(ctx, 3) == 3
+    t = W.random_multilabel(56, (12, 14, 16), 2, E=6.0, lam=0.5)
+    t.topo = S.TOPO_SIMPLE
+    ctx, img, lab = S.from_workload(t)
+    tile, ms = S.tile_autotune(ctx.params, img, lab, iters=2)
+    assert tile == S.TILE_DEFAULT and ms[1] == -1.0 and ms[0] > 0
 
 
 # Iterations of the full-size runs compared with the oracle (stepping from the
