@@ -176,7 +176,7 @@ def batch_bench(a):
         # cell shape for the whole batch (one shape per batch): each shape's
         # batch timed over a few iterations from the seeded start
         ms = {}
-        for tile in (S.TILE_DEFAULT, S.TILE_WIDE):
+        for tile in (S.TILE_DEFAULT, S.TILE_WIDE, S.TILE_TALL):
             cs = contexts(tile)
             Bt = S.Batch(len(cs))
             for k, c in enumerate(cs):
@@ -196,8 +196,10 @@ def batch_bench(a):
             ms[tile] = (time.perf_counter() - t0) * 1e3 / TUNE_ITERS
             Bt.close()
             del cs
-        # as the library's autotuner: the default unless the other is 1 % faster
-        tile = S.TILE_WIDE if ms[S.TILE_WIDE] < 0.99 * ms[S.TILE_DEFAULT] else S.TILE_DEFAULT
+        # as the library's autotuner: the fastest other shape if it beats the
+        # default by 1 %, else the default
+        alt = min((S.TILE_WIDE, S.TILE_TALL), key=ms.get)
+        tile = alt if ms[alt] < 0.99 * ms[S.TILE_DEFAULT] else S.TILE_DEFAULT
         tune = {"chosen": tile_name(2, tile), "iters": TUNE_ITERS,
                 "ms_per_iter": {tile_name(2, k): v for k, v in ms.items()}}
     else:
@@ -326,7 +328,7 @@ def parse():
     ap.add_argument("--topo", action="store_true",
                     help="ranked acceptance with topological control (simple points)")
     ap.add_argument("--tile", type=int, default=None,
-                    help="cell shape: 0 default (8^3 / 16^2), 1 wide (16x8x8 / 16x32); "
+                    help="cell shape: 0 default (8^3 / 16^2), 1 wide (16x8x8 / 16x32), 2 tall (2D: 16x64); "
                          "default: the faster on this workload (autotuner, before the timed region)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 256 MiB copy used to calibrate byte counters")
@@ -354,7 +356,7 @@ def tile_name(ndim, tile):
     """Cell shape of a context as voxels (x by y (by z))."""
     if ndim == 3:
         return "16x8x8" if tile else "8x8x8"
-    return "16x32" if tile else "16x16"
+    return f"16x{16 << tile}"
 
 
 def cpu_baseline(w, budget_s):
@@ -413,7 +415,7 @@ def main():
         del img0, lab0
         w.tile = tile
         tune = {"chosen": tile_name(w.ndim, tile), "iters": TUNE_ITERS,
-                "ms_per_iter": {tile_name(w.ndim, k): ms[k] for k in (0, 1) if ms[k] >= 0}}
+                "ms_per_iter": {tile_name(w.ndim, k): ms[k] for k in range(3) if ms[k] >= 0}}
     ctx, img, lab = S.from_workload(w)
     S.init_labels(ctx, img, lab)
     n0 = S.particle_count(ctx)

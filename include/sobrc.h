@@ -84,13 +84,14 @@ enum { SOBRC_MODE_SOBOLEV = 0, SOBRC_MODE_L2 = 1, SOBRC_MODE_AUTO = 2 };
 enum { SOBRC_TOPO_OFF = 0, SOBRC_TOPO_SIMPLE = 1 };
 /* Cell lists ("Discrete particle approximation", text after Eq. (6):
  * particles binned in cells so that the Eq. (6) sums visit only neighbouring
- * cells; the paper's cells have edge E/2).  Here a cell is a tile of the image, and the results do not
- * depend on its shape (every sum tests the integer distance), only the
- * speed: DEFAULT = 8x8x8 voxels in 3D, 16x16 pixels in 2D; WIDE = twice as
- * long along one axis (16x8x8 in 3D, 16x32 in 2D), so fewer, fuller tiles and
- * less halo per particle.  tile_autotune times both on a given image.  WIDE
- * is not available with topological control. */
-enum { SOBRC_TILE_DEFAULT = 0, SOBRC_TILE_WIDE = 1 };
+ * cells; the paper's cells have edge E/2).  Here a cell is a tile of the
+ * image, and the results do not depend on its shape (every sum tests the
+ * integer distance), only the speed: DEFAULT = 8x8x8 voxels in 3D, 16x16
+ * pixels in 2D; WIDE = twice as long along one axis (16x8x8 in 3D, 16x32 in
+ * 2D); TALL (2D only) = 16x64 pixels.  Longer tiles are fewer and fuller, with
+ * less halo per particle.  tile_autotune times the shapes on a given image.
+ * Only DEFAULT is available with topological control. */
+enum { SOBRC_TILE_DEFAULT = 0, SOBRC_TILE_WIDE = 1, SOBRC_TILE_TALL = 2 };
 /* Deconvolving image model (Methods, Eq. (8): J = s_theta(Gamma) * K), used
  * when params.psf_sigma > 0.  K is a separable Gaussian point-spread function:
  * per axis the taps exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma),
@@ -117,7 +118,7 @@ typedef struct {
     int32_t noise;         /* SOBRC_NOISE_GAUSS or SOBRC_NOISE_POISSON */
     int32_t topo;          /* SOBRC_TOPO_OFF or SOBRC_TOPO_SIMPLE (acceptance, see below) */
     double psf_sigma;      /* 0, or the width (pixels, <= 16) of a Gaussian PSF: deconvolving model */
-    int32_t tile;          /* SOBRC_TILE_DEFAULT or SOBRC_TILE_WIDE: shape of the cells (see below) */
+    int32_t tile;          /* SOBRC_TILE_*: shape of the cells (see below) */
 } sobrc_params;
 
 typedef struct sobrc_ctx sobrc_ctx;
@@ -256,11 +257,11 @@ int32_t get_gradient_mode(sobrc_ctx* ctx, int32_t* h_switch_iter, void* stream);
  * `iters` iterations (1..1000) of `mode` without a tolerance stop from
  * d_labels on d_image (int32 labels and the image as for init_labels),
  * after two warm-up iterations from the same start, and times them with HIP
- * events on `stream`, in two rounds with the shapes alternating.  h_ms[2]
+ * events on `stream`, in two rounds with the shapes alternating.  h_ms[3]
  * receives the milliseconds per iteration (the faster round) of
- * SOBRC_TILE_DEFAULT and SOBRC_TILE_WIDE (-1 for a shape not admitted);
- * *h_tile is SOBRC_TILE_WIDE if that is at least 1 % faster, else the
- * default.  Results do not depend on the shape, so a caller then creates its
+ * SOBRC_TILE_DEFAULT, SOBRC_TILE_WIDE and SOBRC_TILE_TALL (-1 for a shape not
+ * admitted); *h_tile is the fastest other shape if that is at least 1 %
+ * faster than the default, else the default.  Results do not depend on the shape, so a caller then creates its
  * context with that tile.  d_workspace: device memory of at
  * least tile_autotune_workspace_size bytes, 256-byte aligned, owned by the
  * caller; its contents are scratch.  Synchronous.  EINVAL for NULL arguments

@@ -79,9 +79,12 @@ int32_t validate(const sobrc_params* p)
     if (p->psf_sigma > 0.0 && (p->model != SOBRC_PC || p->noise != SOBRC_NOISE_GAUSS || p->max_labels > kDeconvM))
         return fail(SOBRC_EINVAL, "the deconvolving model needs SOBRC_PC, SOBRC_NOISE_GAUSS and max_labels <= %d",
                     kDeconvM);
-    if (p->tile != SOBRC_TILE_DEFAULT && p->tile != SOBRC_TILE_WIDE)
-        return fail(SOBRC_EINVAL, "tile must be SOBRC_TILE_DEFAULT or SOBRC_TILE_WIDE (got %d)", p->tile);
-    if (p->tile == SOBRC_TILE_WIDE && p->topo != SOBRC_TOPO_OFF)
+    if (p->tile != SOBRC_TILE_DEFAULT && p->tile != SOBRC_TILE_WIDE && p->tile != SOBRC_TILE_TALL)
+        return fail(SOBRC_EINVAL, "tile must be SOBRC_TILE_DEFAULT, SOBRC_TILE_WIDE or SOBRC_TILE_TALL (got %d)",
+                    p->tile);
+    if (p->tile == SOBRC_TILE_TALL && p->ndim != 2)
+        return fail(SOBRC_EINVAL, "SOBRC_TILE_TALL is a 2D shape");
+    if (p->tile != SOBRC_TILE_DEFAULT && p->topo != SOBRC_TOPO_OFF)
         return fail(SOBRC_EINVAL, "topological control runs on the default tile shape only");
     return SOBRC_OK;
 }
@@ -108,7 +111,7 @@ Geom make_geom(const sobrc_params* p)
     g.ny = p->ny;
     g.nz = p->ndim == 3 ? p->nz : 1;
     g.ndim = p->ndim;
-    g.wide = p->tile == SOBRC_TILE_WIDE ? 1 : 0;
+    g.wide = p->tile;
     if (p->ndim == 3) {
         g.tsx = g.wide ? 4 : 3;  // 8x8x8 or 16x8x8 voxel tiles
         g.tsy = g.tsz = 3;
@@ -116,8 +119,8 @@ Geom make_geom(const sobrc_params* p)
         g.sz = 20;
         g.mx = g.my = g.mz = 1023u;
     } else {
-        g.tsx = 4;                  // 16x16 or 16x32 pixel tiles
-        g.tsy = g.wide ? 5 : 4;
+        g.tsx = 4;                  // 16x16, 16x32 or 16x64 pixel tiles
+        g.tsy = 4 + g.wide;
         g.tsz = 0;
         g.sy = 16;
         g.sz = 31;
@@ -903,17 +906,30 @@ int32_t get_gradient_mode(sobrc_ctx* c, int32_t* h_switch_iter, void* stream)
     return SOBRC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Tile shapes that parameters admit (the others are not tried by the autotuner).
+bool tile_admitted(const sobrc_params& q, int k)
+{
+    return k == SOBRC_TILE_DEFAULT || (q.topo == SOBRC_TOPO_OFF && (k == SOBRC_TILE_WIDE || q.ndim == 2));
+}
+constexpr int kTileShapes = 3;
+}  // namespace
+
+extern "C" {
+
 int32_t tile_autotune_workspace_size(const sobrc_params* params, size_t* bytes)
 {
     if (!params || !bytes)
         return fail(SOBRC_EINVAL, "params and bytes must be non-NULL");
     size_t most = 0;
-    for (int k = SOBRC_TILE_DEFAULT; k <= SOBRC_TILE_WIDE; ++k) {
+    for (int k = 0; k < kTileShapes; ++k) {
         sobrc_params q = *params;
         q.tile = k;
         size_t n = 0;
-        if (k == SOBRC_TILE_WIDE && q.topo != SOBRC_TOPO_OFF)
-            continue;  // not admitted: not tried
+        if (!tile_admitted(q, k))
+            continue;  // not tried
         SOBRC_TRY(workspace_size(&q, &n));
         most = n > most ? n : most;
     }
@@ -938,14 +954,15 @@ int32_t tile_autotune(const sobrc_params* params, const void* d_image, const int
         return fail(SOBRC_EDEVICE, "hipEventCreate");
     }
     int32_t rc = SOBRC_OK;
-    h_ms[SOBRC_TILE_DEFAULT] = h_ms[SOBRC_TILE_WIDE] = -1.0;
+    for (int k = 0; k < kTileShapes; ++k)
+        h_ms[k] = -1.0;
     // two rounds, shapes alternating; each shape keeps its faster round
     for (int round = 0; round < 2 && rc == SOBRC_OK; ++round)
-        for (int k = SOBRC_TILE_DEFAULT; k <= SOBRC_TILE_WIDE && rc == SOBRC_OK; ++k) {
+        for (int k = 0; k < kTileShapes && rc == SOBRC_OK; ++k) {
             sobrc_params q = *params;
             q.tile = k;
-            if (k == SOBRC_TILE_WIDE && q.topo != SOBRC_TOPO_OFF)
-                continue;  // not admitted
+            if (!tile_admitted(q, k))
+                continue;
             sobrc_ctx* c = nullptr;
             rc = ctx_create(&q, d_workspace, bytes, &c);
             if (rc != SOBRC_OK)
@@ -973,11 +990,14 @@ int32_t tile_autotune(const sobrc_params* params, const void* d_image, const int
             const double per = (double)ms / (double)(done > 0 ? done : 1);
             h_ms[k] = h_ms[k] < 0.0 || per < h_ms[k] ? per : h_ms[k];
         }
-    // the default shape unless the other is at least 1 % faster (timing noise
-    // is of that order)
-    int best = SOBRC_TILE_DEFAULT;
-    if (h_ms[SOBRC_TILE_WIDE] >= 0.0 && h_ms[SOBRC_TILE_WIDE] < 0.99 * h_ms[SOBRC_TILE_DEFAULT])
-        best = SOBRC_TILE_WIDE;
+    // the fastest other shape if it beats the default by at least 1 % (timing
+    // noise is of that order), else the default
+    int best = SOBRC_TILE_DEFAULT, alt = -1;
+    for (int k = 1; k < kTileShapes; ++k)
+        if (h_ms[k] >= 0.0 && (alt < 0 || h_ms[k] < h_ms[alt]))
+            alt = k;
+    if (alt >= 0 && h_ms[alt] < 0.99 * h_ms[SOBRC_TILE_DEFAULT])
+        best = alt;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc == SOBRC_OK)

@@ -17,11 +17,12 @@ constexpr int kMaxGrid = 2048;     // blocks of the particle and emission kernel
 constexpr int kPsLdsMax = 64 * 1024;  // LDS bound of the tile-staged PS L2 gradient
 
 // Tile shapes (cells of the particle lists): the default 8x8x8 voxels in 3D
-// and 16x16 pixels in 2D, or the wide shape, twice as long along one axis
-// (16x8x8 in 3D, along x; 16x32 in 2D, along y).  Every shape keeps at most
-// 16 pixels per tile row and at most 64 rows, the emission slot's format.
+// and 16x16 pixels in 2D (wide = 0); the wide shape, twice as long along one
+// axis (16x8x8 in 3D, along x; 16x32 in 2D, along y; wide = 1); in 2D also
+// the tall shape 16x64 (wide = 2).  Every shape keeps at most 16 pixels per
+// tile row and at most 64 rows, the emission slot's format.
 __host__ __device__ constexpr int tile_ex(int nd, int wide) { return nd == 3 ? (wide ? 16 : 8) : 16; }
-__host__ __device__ constexpr int tile_ey(int nd, int wide) { return nd == 3 ? 8 : (wide ? 32 : 16); }
+__host__ __device__ constexpr int tile_ey(int nd, int wide) { return nd == 3 ? 8 : (16 << wide); }
 __host__ __device__ constexpr int tile_ez(int nd) { return nd == 3 ? 8 : 1; }
 
 // Largest axis offset h with h*h < T: the halo a Sobolev brick needs.
@@ -91,7 +92,7 @@ constexpr int kTopoMaxPasses = 4096;  // passes of the finishing block over the 
 struct Geom {
     int nx, ny, nz, ndim;
     int tsx, tsy, tsz;          // log2 of the tile edge per axis
-    int wide;                   // tile shape: 0 default, 1 wide (tile_ex/ey/ez)
+    int wide;                   // tile shape: 0 default, 1 wide, 2 tall (2D; tile_ex/ey/ez)
     int ntx, nty, ntz, ntiles;  // tiles per axis, total
     int sy, sz;                 // particle position packing: x | y << sy | z << sz
     unsigned mx, my, mz;        // field masks after shifting

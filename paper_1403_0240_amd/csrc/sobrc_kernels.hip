@@ -2763,12 +2763,16 @@ hipError_t launch_sobolev(const Geom& g, const Bufs& b, const SobW& sw, int cur,
             hipLaunchKernelGGL((k_sobolev_brick<ND, H, false, WIDE>), gd, bd, 0, s, g, b, sw, cur, in, out, gated); \
         return hipGetLastError();                                                                  \
     }
-#define SOBRC_BRICK(ND, H) SOBRC_BRICK_W(ND, H, 0) SOBRC_BRICK_W(ND, H, 1)
+#define SOBRC_BRICK(ND, H) SOBRC_BRICK_W(ND, H, 0) SOBRC_BRICK_W(ND, H, 1) SOBRC_BRICK_TALL##ND(H)
+#define SOBRC_BRICK_TALL3(H)
+#define SOBRC_BRICK_TALL2(H) SOBRC_BRICK_W(2, H, 2)
     SOBRC_BRICK(3, 1) SOBRC_BRICK(3, 2) SOBRC_BRICK(3, 3) SOBRC_BRICK(3, 4)
     SOBRC_BRICK(2, 1) SOBRC_BRICK(2, 2) SOBRC_BRICK(2, 3) SOBRC_BRICK(2, 4)
     SOBRC_BRICK(2, 5) SOBRC_BRICK(2, 6) SOBRC_BRICK(2, 7) SOBRC_BRICK(2, 8)
 #undef SOBRC_BRICK
 #undef SOBRC_BRICK_W
+#undef SOBRC_BRICK_TALL3
+#undef SOBRC_BRICK_TALL2
     return hipErrorInvalidValue;
 }
 
@@ -2812,7 +2816,7 @@ hipError_t launch_count(const Geom& g, const Bufs& b, int cur, int gated, int al
             hipLaunchKernelGGL((k_count_list<ND, WIDE>), dim3(gl), dim3(kBlock), 0, s, g, b, gated);      \
         }                                                                                                  \
     }
-    SOBRC_COUNT(3, 0) SOBRC_COUNT(3, 1) SOBRC_COUNT(2, 0) SOBRC_COUNT(2, 1)
+    SOBRC_COUNT(3, 0) SOBRC_COUNT(3, 1) SOBRC_COUNT(2, 0) SOBRC_COUNT(2, 1) SOBRC_COUNT(2, 2)
 #undef SOBRC_COUNT
     return hipGetLastError();
 }
@@ -3119,12 +3123,16 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
                                t.d, t.par, t.tpre, ns, sw, flags);                                            \
         done = true;                                                                                          \
     }
-#define SOBRC_BRICK(ND, H) SOBRC_BRICK_W(ND, H, 0) SOBRC_BRICK_W(ND, H, 1)
+#define SOBRC_BRICK(ND, H) SOBRC_BRICK_W(ND, H, 0) SOBRC_BRICK_W(ND, H, 1) SOBRC_BRICK_TALL##ND(H)
+#define SOBRC_BRICK_TALL3(H)
+#define SOBRC_BRICK_TALL2(H) SOBRC_BRICK_W(2, H, 2)
             SOBRC_BRICK(3, 1) SOBRC_BRICK(3, 2) SOBRC_BRICK(3, 3) SOBRC_BRICK(3, 4)
             SOBRC_BRICK(2, 1) SOBRC_BRICK(2, 2) SOBRC_BRICK(2, 3) SOBRC_BRICK(2, 4)
             SOBRC_BRICK(2, 5) SOBRC_BRICK(2, 6) SOBRC_BRICK(2, 7) SOBRC_BRICK(2, 8)
 #undef SOBRC_BRICK
 #undef SOBRC_BRICK_W
+#undef SOBRC_BRICK_TALL3
+#undef SOBRC_BRICK_TALL2
         }
         if (!done)
             hipLaunchKernelGGL(kb_sobolev_generic, gd, dim3(kSobBlock), g0.sob_lds, s, t.d, t.par, t.off, ns,
@@ -3140,7 +3148,7 @@ hipError_t launch_batch_step(const BatchTab& t, const unsigned* totals, const Ge
         hipLaunchKernelGGL((kb_count_list<ND, WIDE>), persistent_grid(totals[kPhList]), dim3(kBlock), 0, s,  \
                            t.d, t.off, ns);                                                                  \
     }
-    SOBRC_COUNT(3, 0) SOBRC_COUNT(3, 1) SOBRC_COUNT(2, 0) SOBRC_COUNT(2, 1)
+    SOBRC_COUNT(3, 0) SOBRC_COUNT(3, 1) SOBRC_COUNT(2, 0) SOBRC_COUNT(2, 1) SOBRC_COUNT(2, 2)
 #undef SOBRC_COUNT
     hipLaunchKernelGGL(kb_scan, dim3(nsc), dim3(kScanThreads), 0, s, t.d, t.par, t.off, ns, tol, flags);
     hipLaunchKernelGGL(kb_write, persistent_grid(totals[kPhEmit]), dim3(kBlock), 0, s, t.d, t.par, t.off, ns, l2,

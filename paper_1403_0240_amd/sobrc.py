@@ -20,7 +20,7 @@ PC, PS = 0, 1
 NOISE_GAUSS, NOISE_POISSON = 0, 1
 MODE_SOBOLEV, MODE_L2, MODE_AUTO = 0, 1, 2
 TOPO_OFF, TOPO_SIMPLE = 0, 1
-TILE_DEFAULT, TILE_WIDE = 0, 1
+TILE_DEFAULT, TILE_WIDE, TILE_TALL = 0, 1, 2
 K_L2DIFF, K_SOBOLEV, K_FLIP, K_COUNT, K_SCAN, K_WRITE, K_TOPO, K_DECONV = range(8)
 KERNEL_NAMES = ("k_l2diff", "k_sobolev", "k_flip", "k_count", "k_scan", "k_write", "k_topo",
                 "k_deconv")
@@ -288,16 +288,17 @@ def get_labels_u16(ctx: Context, out=None, stream=None) -> torch.Tensor:
 
 def tile_autotune(params: Params, image, labels, iters: int = 4, mode=MODE_SOBOLEV, stream=None):
     """Time `iters` iterations with each cell shape on this image (device
-    tensors as for init_labels); returns (faster TILE_*, [ms per iteration of
-    TILE_DEFAULT, TILE_WIDE]) (-1 for a shape the parameters do not admit)."""
+    tensors as for init_labels); returns (chosen TILE_*, [ms per iteration of
+    TILE_DEFAULT, TILE_WIDE, TILE_TALL]) (-1 for a shape the parameters do not
+    admit)."""
     nb = C.c_size_t(0)
     _check(lib().tile_autotune_workspace_size(C.byref(params), C.byref(nb)))
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=image.device)
     tile = C.c_int32(0)
-    ms = (C.c_double * 2)()
+    ms = (C.c_double * 3)()
     _check(lib().tile_autotune(C.byref(params), _ptr(image), _ptr(labels), int(iters), mode, _ptr(ws),
                                nb.value, C.byref(tile), ms, _stream(stream)))
-    return tile.value, [ms[0], ms[1]]
+    return tile.value, [ms[0], ms[1], ms[2]]
 
 
 def get_region_stats(ctx: Context, stream=None):

@@ -49,8 +49,9 @@ def _p(**kw):
                                 dict(psf_sigma=-1.0), dict(psf_sigma=16.5),
                                 dict(psf_sigma=2.0, model=S.PS, ps_radius=3),
                                 dict(psf_sigma=2.0, noise=S.NOISE_POISSON),
-                                dict(psf_sigma=2.0, max_labels=5), dict(tile=2), dict(tile=-1),
-                                dict(tile=S.TILE_WIDE, topo=S.TOPO_SIMPLE)])
+                                dict(psf_sigma=2.0, max_labels=5), dict(tile=3), dict(tile=-1),
+                                dict(tile=S.TILE_WIDE, topo=S.TOPO_SIMPLE),
+                                dict(tile=S.TILE_TALL, topo=S.TOPO_SIMPLE)])
 def test_bad_params(L, kw):
     n = C.c_size_t(0)
     assert L.workspace_size(C.byref(_p(**kw)), C.byref(n)) == S.EINVAL
@@ -68,14 +69,23 @@ def test_tile_shapes(L):
         assert L.workspace_size(C.byref(d), C.byref(nd)) == S.OK
         assert L.workspace_size(C.byref(w), C.byref(nw)) == S.OK
         assert L.tile_autotune_workspace_size(C.byref(w), C.byref(na)) == S.OK
-        assert na.value == max(nd.value, nw.value)
+        sizes = [nd.value, nw.value]
+        if len(shape) == 2:
+            t = S.make_params(shape, "float32", 6.0, 0.1, max_particles=1000, tile=S.TILE_TALL)
+            nt = C.c_size_t(0)
+            assert L.workspace_size(C.byref(t), C.byref(nt)) == S.OK
+            sizes.append(nt.value)
+        else:
+            t = S.make_params(shape, "float32", 6.0, 0.1, max_particles=1000, tile=S.TILE_TALL)
+            assert L.workspace_size(C.byref(t), C.byref(C.c_size_t())) == S.EINVAL  # 2D only
+        assert na.value == max(sizes)
     t = S.make_params((9, 40, 33), "float32", 6.0, 0.1, max_particles=1000, topo=S.TOPO_SIMPLE)
     nt, na = C.c_size_t(0), C.c_size_t(0)
     assert L.workspace_size(C.byref(t), C.byref(nt)) == S.OK
     assert L.tile_autotune_workspace_size(C.byref(t), C.byref(na)) == S.OK
     assert na.value == nt.value  # the wide shape is not tried with topological control
     fake = C.c_void_p(1 << 20)  # never dereferenced: rejected before any device call
-    tile, ms = C.c_int32(0), (C.c_double * 2)()
+    tile, ms = C.c_int32(0), (C.c_double * 3)()
     ta = L.tile_autotune
     assert ta(None, fake, fake, 4, 0, fake, 1 << 20, C.byref(tile), ms, None) == S.EINVAL
     assert ta(C.byref(w), None, fake, 4, 0, fake, 1 << 20, C.byref(tile), ms, None) == S.EINVAL

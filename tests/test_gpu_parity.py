@@ -99,6 +99,22 @@ CASES.update({f"{n}_wide": _wide(CASES[n]) for n in [
     "many_labels_3d", "ps2d_r8", "ps3d_r4_u16", "thin3d_nz2", "row2d_ny1", "col2d_nx1"]})
 CASES["blobs3d_long_wide"] = _wide(lambda: W.random_multilabel(52, (18, 20, 45), 3, E=6.0, lam=0.5))
 CASES["blobs2d_tall_wide"] = _wide(lambda: W.random_multilabel(53, (75, 41), 3, E=8.0, lam=0.4))
+
+
+def _tall(make):
+    def w():
+        x = make()
+        x.tile = S.TILE_TALL
+        return x
+    return w
+
+
+# 16x64-pixel cells: images shorter than a tile, several tiles with ragged
+# tails, multi-label and PS cases
+CASES.update({f"{n}_tall": _tall(CASES[n]) for n in [
+    "rand2d_blobs", "rand2d_ps", "disk2d_128", "ps2d_r8", "many_labels_2d", "row2d_ny1", "col2d_nx1",
+    "wide_kernel_2d"]})
+CASES["blobs2d_long_tall"] = _tall(lambda: W.random_multilabel(57, (150, 37), 3, E=8.0, lam=0.4))
 CAPS["many_labels_3d_wide"] = 16384
 
 
@@ -389,7 +405,7 @@ def test_tile_shapes_agree_full_size(name):
     w = W.make(name)
     print(f"[case {name} tile shapes]", flush=True)
     out = {}
-    for tile in (S.TILE_DEFAULT, S.TILE_WIDE):
+    for tile in (S.TILE_DEFAULT, S.TILE_WIDE) + ((S.TILE_TALL,) if w.ndim == 2 else ()):
         w.tile = tile
         ctx, img, lab = gpu_state(w)
         lin, a, b = gpu_particles(ctx)
@@ -404,12 +420,13 @@ def test_tile_shapes_agree_full_size(name):
             labels.append(S.get_labels(ctx).cpu().numpy())
         out[tile] = (key[order], dl2[:n].cpu().numpy()[order], dh1[:n].cpu().numpy()[order], labels)
         del ctx, img, lab
-    d, wd = out[S.TILE_DEFAULT], out[S.TILE_WIDE]
-    assert np.array_equal(d[0], wd[0]), "particle sets differ"
-    assert np.array_equal(d[1], wd[1]), "L2 gradients differ"
-    assert np.array_equal(d[2], wd[2]), "Sobolev gradients differ"
-    for k, (x, y) in enumerate(zip(d[3], wd[3])):
-        assert np.array_equal(x, y), f"labels differ after iteration {k + 1}"
+    d = out[S.TILE_DEFAULT]
+    for tile, wd in out.items():
+        assert np.array_equal(d[0], wd[0]), f"tile {tile}: particle sets differ"
+        assert np.array_equal(d[1], wd[1]), f"tile {tile}: L2 gradients differ"
+        assert np.array_equal(d[2], wd[2]), f"tile {tile}: Sobolev gradients differ"
+        for k, (x, y) in enumerate(zip(d[3], wd[3])):
+            assert np.array_equal(x, y), f"tile {tile}: labels differ after iteration {k + 1}"
 
 
 def test_tile_autotune():
@@ -420,8 +437,9 @@ def test_tile_autotune():
         ctx, img, lab = S.from_workload(w)
         tile, ms = S.tile_autotune(ctx.params, img, lab, iters=3)
         assert tile in (S.TILE_DEFAULT, S.TILE_WIDE)
-        assert ms[0] > 0 and ms[1] > 0
-        assert tile == (S.TILE_WIDE if ms[1] < 0.99 * ms[0] else S.TILE_DEFAULT)
+        assert ms[0] > 0 and ms[1] > 0 and (ms[2] > 0) == (w.ndim == 2) and (ms[2] == -1.0) == (w.ndim == 3)
+        alt = 1 if w.ndim == 3 or ms[1] <= ms[2] else 2
+        assert tile == (alt if ms[alt] < 0.99 * ms[0] else S.TILE_DEFAULT)
         w.tile = tile
         ctx, img, lab = gpu_state(w)
         assert S.run(ctx, 3) == 3
@@ -429,7 +447,7 @@ def test_tile_autotune():
     t.topo = S.TOPO_SIMPLE
     ctx, img, lab = S.from_workload(t)
     tile, ms = S.tile_autotune(ctx.params, img, lab, iters=2)
-    assert tile == S.TILE_DEFAULT and ms[1] == -1.0 and ms[0] > 0
+    assert tile == S.TILE_DEFAULT and ms[1] == ms[2] == -1.0 and ms[0] > 0
 
 
 # Iterations of the full-size runs compared with the oracle (stepping from the
