@@ -73,14 +73,10 @@ class _Pool:
         return [(k, j) for k, j in enumerate(self.jobs) if j is not None]
 
 
-def footprint(w, capacity: int) -> int:
+def footprint(w, capacity: int, tile: int = 0) -> int:
     """Device bytes a request holds while resident: its context workspace
     plus the image."""
-    p = S.make_params(w.image.shape, str(w.image.dtype), w.E, w.lam, model=w.model,
-                      ps_radius=w.ps_radius, eps=w.eps, max_labels=w.max_labels,
-                      max_particles=capacity, noise=getattr(w, "noise", 0),
-                      topo=getattr(w, "topo", 0), psf_sigma=getattr(w, "psf_sigma", 0.0))
-    return S.workspace_size(p) + w.image.nbytes
+    return S.workspace_size(S.workload_params(w, capacity, tile)) + w.image.nbytes
 
 
 def default_capacity(w) -> int:
@@ -93,10 +89,12 @@ class Server:
     hbm_budget: device bytes the resident requests may hold together;
     slots: slots per pool; tol: flip tolerance (stop when flips < tol * N);
     max_iters: per-request iteration cap; tick: iterations enqueued per pool
-    between host looks."""
+    between host looks; tiles: cell shape per image dimension (sobrc.TILE_*;
+    results do not depend on it)."""
 
     def __init__(self, hbm_budget: int = 8 << 30, slots: int = 64, tol: float = 1e-3,
-                 max_iters: int = 500, tick: int = 4, mode: int = S.MODE_AUTO):
+                 max_iters: int = 500, tick: int = 4, mode: int = S.MODE_AUTO, tiles=None):
+        self.tiles = dict(tiles or {})
         self.budget, self.slots, self.tol = hbm_budget, slots, tol
         self.max_iters, self.tick, self.mode = max_iters, tick, mode
         self.pools: dict[tuple, _Pool] = {}
@@ -121,14 +119,17 @@ class Server:
                              f"are not served in batches")
         if req.capacity is None:
             req.capacity = default_capacity(req.work)
-        req.footprint = footprint(req.work, req.capacity)
+        req.footprint = footprint(req.work, req.capacity, self._tile(req.work))
         if req.footprint > self.budget:
             raise ValueError(f"request {req.rid} needs {req.footprint} bytes > budget {self.budget}")
         self.waiting.append(req)
 
+    def _tile(self, w) -> int:
+        return self.tiles.get(w.ndim, getattr(w, "tile", 0))
+
     # ------------------------------------------------------------ admission
     def _pool_of(self, w) -> _Pool:
-        key = (w.ndim, float(w.E), float(w.eps))
+        key = (w.ndim, float(w.E), float(w.eps), self._tile(w))
         if key not in self.pools:
             self.pools[key] = _Pool(self.slots)
         return self.pools[key]
@@ -147,7 +148,7 @@ class Server:
             w = req.work
             cap = req.capacity
             with torch.cuda.stream(self.admit_stream):
-                ctx, img, lab = S.from_workload(w, max_particles=cap)
+                ctx, img, lab = S.from_workload(w, max_particles=cap, tile=self._tile(w))
                 S.init_labels(ctx, img, lab, stream=self.admit_stream)
                 del lab
             pool.ready.append(_Job(req, ctx, img, cap))
