@@ -300,7 +300,7 @@ def serve_bench(a):
     rec = {
         "metric": "served images/s + p99 (continuous batching, Poisson arrivals)",
         "value": st["images_per_s"], "unit": "images/s", "n_gpus": 1,
-        "steps": len(done), "warmup": 4, "ms_per_step": 1e3 * st["span_s"] / max(len(done), 1),
+        "steps": len(done), "warmup": len(reqs), "ms_per_step": 1e3 * st["span_s"] / max(len(done), 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve_mix", "requests": len(done), "rate_per_s": 50.0,
