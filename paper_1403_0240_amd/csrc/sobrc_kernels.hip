@@ -691,6 +691,18 @@ __device__ __forceinline__ bool slot_tile(const Geom& g, unsigned j, unsigned& t
     return u < ls && t < (unsigned)g.ntiles;
 }
 
+// Items [a0, a1) of [0, na) for this block: contiguous chunks, consecutive
+// chunks on the same XCD (blocks are dealt to the 8 XCDs round-robin), so
+// that work on neighbouring tiles shares one L2.  Grids that are not a
+// multiple of 8 take chunks in block order.
+__device__ __forceinline__ void xcd_chunk(unsigned na, VB vb, unsigned& a0, unsigned& a1)
+{
+    const unsigned G = vb.n;
+    const unsigned L = (G & 7u) ? vb.id : (vb.id & 7u) * (G >> 3) + (vb.id >> 3);
+    a0 = (unsigned)((unsigned long long)L * na / G);
+    a1 = (unsigned)((unsigned long long)(L + 1) * na / G);
+}
+
 __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned epoch, int all_dirty)
 {
     return all_dirty || b.dirty[t] == epoch;
@@ -758,11 +770,16 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
     count_body<ND, WIDE>(g, b, cur, gated, all_dirty, VB{blockIdx.x, gridDim.x});
 }
 
-// Dirty tiles listed by count_body, counted with one wave each: every block
-// forms the exclusive prefix of the per-block list lengths (two 16-byte loads
-// per thread) and the waves of all blocks take list items round-robin, so a
-// cluster of dirty tiles in one emission block no longer serialises on its
-// four waves.  The items also go to a flat list (tile ids) for the write
+// Dirty tiles listed by count_body, counted with one wave each.  Emission
+// block j lists dirty tiles of the (j mod 8)-th eighth of the tile order
+// (count_body's slot mapping), so the lists are concatenated in key order
+// k = (j mod 8) * ceil(ge / 8) + j / 8: eighth by eighth, which puts
+// neighbouring tiles close together in the concatenation.  Every block forms
+// the exclusive prefix of the list lengths in key order and takes an
+// XCD-contiguous, equal share of the items, one per wave in turn: the dirty
+// tiles of one region are counted on one XCD (their label boxes overlap, so
+// they share lines of its L2), and every wave has at most one more item than
+// any other.  The items also go to a flat list (tile ids) for the write
 // kernel.
 template <int ND, int WIDE>
 __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, int gated, VB vb)
@@ -772,36 +789,39 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     __shared__ unsigned s_red[kBlock / 64];
     static_assert(kMaxGrid == 8 * kBlock, "eight list lengths per thread");
     const int ge = g.ge;
+    const int gk = (ge + 7) >> 3, nkey = 8 * gk;  // nkey <= kMaxGrid (ge <= kMaxGrid, a multiple of 8)
     const int i0 = (int)threadIdx.x * 8;
-    const uint4* dc = (const uint4*)b.dcnt;  // kMaxGrid entries; only those < ge are read
     // the list lengths are loaded with the stop flag (in bounds either way)
-    const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-    const uint4 q0 = i0 < ge ? dc[2 * threadIdx.x] : z4, q1 = i0 + 4 < ge ? dc[2 * threadIdx.x + 1] : z4;
-    if (gated && stopped(b.ds))
-        return;
-    unsigned c[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-    unsigned sum = 0;
+    unsigned c[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        c[k] = i0 + k < ge ? c[k] : 0u;
-        sum += c[k];
+        const int key = i0 + k, e = key / gk, j = (key - e * gk) * 8 + e;
+        c[k] = key < nkey && j < ge ? b.dcnt[j] : 0u;
     }
+    if (gated && stopped(b.ds))
+        return;
+    unsigned sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        sum += c[k];
     unsigned tot;
     unsigned ex = block_exscan_u(sum, s_red, &tot);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        if (i0 + k < ge)
+        if (i0 + k < nkey)
             s_pre[i0 + k] = ex;
         ex += c[k];
     }
     if (threadIdx.x == 0)
-        s_pre[ge] = tot;
+        s_pre[nkey] = tot;
     __syncthreads();
     if (vb.id == 0 && threadIdx.x == 0)
         b.ds->ndirty = tot;
     const int wv = threadIdx.x >> 6;
-    for (unsigned item = vb.id * (kBlock / 64) + wv; item < tot; item += vb.n * (kBlock / 64)) {
-        int lo = 0, hi = ge;  // list block holding item: the largest lo with s_pre[lo] <= item
+    unsigned a0, a1;
+    xcd_chunk(tot, vb, a0, a1);
+    for (unsigned item = a0 + wv; item < a1; item += kBlock / 64) {
+        int lo = 0, hi = nkey;  // key holding item: the largest lo with s_pre[lo] <= item
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (s_pre[mid] <= item)
@@ -809,7 +829,8 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
             else
                 hi = mid;
         }
-        const unsigned pos = (unsigned)lo * kBlock + (item - s_pre[lo]);
+        const int e = lo / gk, j = (lo - e * gk) * 8 + e;
+        const unsigned pos = (unsigned)j * kBlock + (item - s_pre[lo]);
         const unsigned td = b.dlist[pos];
         unsigned cc = wave_count_tile<ND, WIDE>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
@@ -1109,12 +1130,16 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     const unsigned tdv = in ? b.dirty[t] : 0u;
     const unsigned tso = in ? b.tstart[cur][t] : 0u;
     const unsigned base = b.part_off[vb.id], abase = b.part_aoff[vb.id];
-    // this wave's first dirty tile of the flat list: its loads are issued
-    // now, so that they overlap the range's work below
+    // this block's XCD-contiguous share of the flat list of dirty tiles (in
+    // the count's order: neighbouring tiles, whose records are neighbours too,
+    // are written through one L2), one item per wave in turn; the first
+    // item's loads are issued now, so that they overlap the range's work below
     const int wv = threadIdx.x >> 6, lane = lane_id();
-    const unsigned item0 = vb.id * (kBlock / 64) + (unsigned)wv;
     const unsigned nd0 = g.dlistm ? ds->ndirty : 0u;
-    const unsigned tt0 = item0 < nd0 ? b.dflat[item0] : 0u;
+    unsigned ia0, ia1;
+    xcd_chunk(nd0, vb, ia0, ia1);
+    const unsigned item0 = ia0 + (unsigned)wv;
+    const unsigned tt0 = item0 < ia1 ? b.dflat[item0] : 0u;
     if (ds->undo) {
         // the same gradients k_flip decided on in this step
         const float* grad = ((flags & kAuto) && (ds->lmode & 1u)) ? grad_l2 : grad_sob;
@@ -1152,7 +1177,7 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
         return;
     const unsigned epoch = ds->epoch;
     unsigned ctt0 = 0u, pbase0 = 0u, hdr0 = 0u, word0 = 0u, part0 = 0u;
-    if (item0 < nd0) {
+    if (item0 < ia1) {
         ctt0 = b.tcnt[tt0];
         pbase0 = b.part_off[tt0 >> g.lgRe];
         const unsigned* slot = b.tslot + (size_t)tt0 * kSlotWords;
@@ -1208,12 +1233,11 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
                 rec[dst[u]] = r[u];
     }
     if (g.dlistm) {
-        // dirty tiles from the flat list, round-robin over all waves; the
-        // first one's loads went out at the start
-        if (item0 < nd0 && ctt0)
+        // the block's dirty tiles from the flat list, one per wave in turn;
+        // the first one's loads went out at the start
+        if (item0 < ia1 && ctt0)
             wave_write_tile(g, b.lab, tt0, W[wv], hdr0, word0, rec, pbase0 + wave_sum_u(part0));
-        const unsigned nd = nd0;
-        for (unsigned item = item0 + vb.n * (kBlock / 64); item < nd; item += vb.n * (kBlock / 64)) {
+        for (unsigned item = item0 + kBlock / 64; item < ia1; item += kBlock / 64) {
             const unsigned tt = b.dflat[item];
             // every load of the tile is issued before any is used
             const unsigned ctt = b.tcnt[tt];
@@ -1256,18 +1280,6 @@ __global__ __launch_bounds__(kBlock) void k_write(Geom g, Bufs b, const void* im
                                                  const float* __restrict__ grad_l2, int flags, int all_dirty)
 {
     write_body(g, b, img, cur, nxt, grad_sob, grad_l2, flags, all_dirty, VB{blockIdx.x, gridDim.x});
-}
-
-// Items [a0, a1) of [0, na) for this block: contiguous chunks, consecutive
-// chunks on the same XCD (blocks are dealt to the 8 XCDs round-robin), so
-// that work on neighbouring tiles shares one L2.  Grids that are not a
-// multiple of 8 take chunks in block order.
-__device__ __forceinline__ void xcd_chunk(unsigned na, VB vb, unsigned& a0, unsigned& a1)
-{
-    const unsigned G = vb.n;
-    const unsigned L = (G & 7u) ? vb.id : (vb.id & 7u) * (G >> 3) + (vb.id >> 3);
-    a0 = (unsigned)((unsigned long long)L * na / G);
-    a1 = (unsigned)((unsigned long long)(L + 1) * na / G);
 }
 
 // --------------------------------------------------- L2 gradient per particle
