@@ -1121,15 +1121,19 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
     __shared__ unsigned s_dl[kBlock];
     __shared__ unsigned s_ndl;
     DevState* ds = b.ds;
-    // this thread's tile of range vb.id (< ge): its loads go out with the
-    // state flags (in bounds whichever way the flags decide)
-    const int t0 = vb.id << g.lgRe, t1 = min(t0 + g.Re, g.ntiles);
+    // the block's emission range: consecutive ranges on one XCD (with a grid
+    // that is a multiple of 8), so that the record lines two neighbouring
+    // ranges share are written through one L2.  This thread's tile of the
+    // range: its loads go out with the state flags (in bounds whichever way
+    // the flags decide)
+    const unsigned rg = (vb.n & 7u) ? vb.id : (vb.id & 7u) * (vb.n >> 3) + (vb.id >> 3);
+    const int t0 = (int)rg << g.lgRe, t1 = min(t0 + g.Re, g.ntiles);
     const int t = t0 + (int)threadIdx.x;
     const bool in = t < t1;
     const unsigned c = in ? b.tcnt[t] : 0;
     const unsigned tdv = in ? b.dirty[t] : 0u;
     const unsigned tso = in ? b.tstart[cur][t] : 0u;
-    const unsigned base = b.part_off[vb.id], abase = b.part_aoff[vb.id];
+    const unsigned base = b.part_off[rg], abase = b.part_aoff[rg];
     // this block's XCD-contiguous share of the flat list of dirty tiles (in
     // the count's order: neighbouring tiles, whose records are neighbours too,
     // are written through one L2), one item per wave in turn; the first
@@ -1187,7 +1191,7 @@ __device__ __forceinline__ void write_body(const Geom& g, const Bufs& b, const v
         for (int k = r0 + lane; k < (int)tt0; k += 64)
             part0 += b.tcnt[k];
     }
-    // range vb.id: offsets, non-empty tile list, and the clean tiles'
+    // range rg: offsets, non-empty tile list, and the clean tiles'
     // records moved unchanged to their new offsets
     const bool dirty = in && (all_dirty || tdv == epoch);
     unsigned tot, totz;
