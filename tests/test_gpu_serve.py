@@ -45,8 +45,8 @@ def requests():
     return out
 
 
-def standalone(w):
-    ctx, img, lab = S.from_workload(w, max_particles=SV.default_capacity(w))
+def standalone(w, tile=None):
+    ctx, img, lab = S.from_workload(w, max_particles=SV.default_capacity(w), tile=tile)
     S.init_labels(ctx, img, lab)
     t = S.run(ctx, MAX_IT, TOL, S.MODE_AUTO)
     return S.get_labels(ctx).cpu().numpy(), t, S.gradient_switch(ctx)
@@ -76,6 +76,25 @@ def test_each_result_same_alone_and_in_mix(realtime):
     stats = SV.latency_stats(done)
     assert stats["p99_s"] >= stats["p50_s"] > 0
     assert all(r.error is None for r in done)
+
+
+def test_wide_cells_served():
+    """A server that puts its 2D requests on 16x32 cells: each such request
+    ends exactly as its stand-alone run on the same cells, the 3D requests as
+    on the default cells, and the labels are copied out through the 16-bit
+    path (uint16 arrays)."""
+    reqs = requests()
+    print(f"[serve wide 2D cells n={len(reqs)}]", flush=True)
+    srv = SV.Server(hbm_budget=1 << 32, slots=3, tol=TOL, max_iters=MAX_IT, tick=3, tiles={2: S.TILE_WIDE})
+    done = {r.rid: r for r in srv.serve(reqs, realtime=False)}
+    srv.close()
+    assert sorted(done) == list(range(len(reqs)))
+    for k, (_, w) in enumerate(reqs):
+        L, t, sw = standalone(w, tile=S.TILE_WIDE if w.ndim == 2 else S.TILE_DEFAULT)
+        r = done[k]
+        assert r.labels.dtype == np.uint16 and r.labels.shape == w.image.shape
+        assert r.iterations == t and r.switch_iter == sw
+        assert np.array_equal(r.labels, L), f"request {k}: labels differ from its stand-alone run"
 
 
 def test_served_results_match_oracle(ora):
