@@ -716,6 +716,36 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     __shared__ WaveEmit W[kBlock / 64];
     __shared__ unsigned s_dl[kBlock];
     __shared__ unsigned s_ndl;
+    __shared__ unsigned s_red[kBlock / 64];
+    if (g.dlistm) {
+        // The dirty tiles go to a flat list that count_list_body counts: the
+        // block takes its emission range as a contiguous run of tiles (Re <=
+        // kBlock), lists the range's dirty tiles in tile order and forms the
+        // range's sums of the clean tiles itself (no atomics).  The loads go
+        // out with the stop flag (in bounds either way).
+        const int tr = (int)(vb.id << g.lgRe) + (int)threadIdx.x;
+        const bool in = (int)threadIdx.x < g.Re && tr < g.ntiles;
+        const unsigned tdv = in ? b.dirty[tr] : 0u;
+        const unsigned ts0 = in ? b.tstart[cur][tr] : 0u, ts1 = in ? b.tstart[cur][tr + 1] : 0u;
+        const unsigned epoch = b.ds->epoch;
+        if (gated && stopped(b.ds))
+            return;
+        const bool dirty = in && (all_dirty || tdv == epoch);
+        const unsigned c = in && !dirty ? ts1 - ts0 : 0u;
+        if (in && !dirty)
+            b.tcnt[tr] = c;
+        unsigned packed, sum;
+        const unsigned pre = block_exscan_u((dirty ? 1u : 0u) | (c ? 1u << 16 : 0u), s_red, &packed);
+        if (dirty)
+            b.dlist[(size_t)vb.id * kBlock + (pre & 0xffffu)] = (unsigned)tr;
+        (void)block_exscan_u(c, s_red, &sum);
+        if (threadIdx.x == 0) {
+            b.dcnt[vb.id] = packed & 0xffffu;
+            b.part_cnt[vb.id] = sum;  // count_list_body adds the dirty tiles' counts
+            b.part_act[vb.id] = packed >> 16;
+        }
+        return;
+    }
     const unsigned G = vb.n;
     const unsigned j = vb.id + threadIdx.x * G;  // G * kBlock >= 8 * ceil(ntiles / 8)
     unsigned t;
@@ -743,13 +773,6 @@ __device__ __forceinline__ void count_body(const Geom& g, const Bufs& b, int cur
     }
     __syncthreads();
     const unsigned ndl = s_ndl;
-    if (g.dlistm) {  // list them; count_list_body balances them over all waves
-        for (unsigned k = threadIdx.x; k < ndl; k += kBlock)
-            b.dlist[(size_t)vb.id * kBlock + k] = s_dl[k];
-        if (threadIdx.x == 0)
-            b.dcnt[vb.id] = ndl;
-        return;
-    }
     const int wv = threadIdx.x >> 6;
     for (unsigned i = wv; i < ndl; i += kBlock / 64) {
         const unsigned td = s_dl[i];
@@ -771,16 +794,14 @@ __global__ __launch_bounds__(kBlock) void k_count(Geom g, Bufs b, int cur, int g
 }
 
 // Dirty tiles listed by count_body, counted with one wave each.  Emission
-// block j lists dirty tiles of the (j mod 8)-th eighth of the tile order
-// (count_body's slot mapping), so the lists are concatenated in key order
-// k = (j mod 8) * ceil(ge / 8) + j / 8: eighth by eighth, which puts
-// neighbouring tiles close together in the concatenation.  Every block forms
-// the exclusive prefix of the list lengths in key order and takes an
-// XCD-contiguous, equal share of the items, one per wave in turn: the dirty
-// tiles of one region are counted on one XCD (their label boxes overlap, so
-// they share lines of its L2), and every wave has at most one more item than
-// any other.  The items also go to a flat list (tile ids) for the write
-// kernel.
+// block j lists the dirty tiles of range j in tile order, so the lists
+// concatenated in block order are the dirty tiles in tile order.  Every block
+// forms the exclusive prefix of the list lengths (two 16-byte loads per
+// thread) and takes an XCD-contiguous, equal share of the items, one per wave
+// in turn: the dirty tiles of one region are counted on one XCD (their label
+// boxes overlap, so they share lines of its L2), and every wave has at most
+// one more item than any other.  The items also go to a flat list (tile ids)
+// for the write kernel.
 template <int ND, int WIDE>
 __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, int gated, VB vb)
 {
@@ -789,31 +810,30 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     __shared__ unsigned s_red[kBlock / 64];
     static_assert(kMaxGrid == 8 * kBlock, "eight list lengths per thread");
     const int ge = g.ge;
-    const int gk = (ge + 7) >> 3, nkey = 8 * gk;  // nkey <= kMaxGrid (ge <= kMaxGrid, a multiple of 8)
     const int i0 = (int)threadIdx.x * 8;
+    const uint4* dc = (const uint4*)b.dcnt;  // kMaxGrid entries; only those < ge are read
     // the list lengths are loaded with the stop flag (in bounds either way)
-    unsigned c[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int key = i0 + k, e = key / gk, j = (key - e * gk) * 8 + e;
-        c[k] = key < nkey && j < ge ? b.dcnt[j] : 0u;
-    }
+    const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+    const uint4 q0 = i0 < ge ? dc[2 * threadIdx.x] : z4, q1 = i0 + 4 < ge ? dc[2 * threadIdx.x + 1] : z4;
     if (gated && stopped(b.ds))
         return;
+    unsigned c[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
     unsigned sum = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 8; ++k) {
+        c[k] = i0 + k < ge ? c[k] : 0u;
         sum += c[k];
+    }
     unsigned tot;
     unsigned ex = block_exscan_u(sum, s_red, &tot);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        if (i0 + k < nkey)
+        if (i0 + k < ge)
             s_pre[i0 + k] = ex;
         ex += c[k];
     }
     if (threadIdx.x == 0)
-        s_pre[nkey] = tot;
+        s_pre[ge] = tot;
     __syncthreads();
     if (vb.id == 0 && threadIdx.x == 0)
         b.ds->ndirty = tot;
@@ -821,7 +841,7 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     unsigned a0, a1;
     xcd_chunk(tot, vb, a0, a1);
     for (unsigned item = a0 + wv; item < a1; item += kBlock / 64) {
-        int lo = 0, hi = nkey;  // key holding item: the largest lo with s_pre[lo] <= item
+        int lo = 0, hi = ge;  // list block holding item: the largest lo with s_pre[lo] <= item
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (s_pre[mid] <= item)
@@ -829,8 +849,7 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
             else
                 hi = mid;
         }
-        const int e = lo / gk, j = (lo - e * gk) * 8 + e;
-        const unsigned pos = (unsigned)j * kBlock + (item - s_pre[lo]);
+        const unsigned pos = (unsigned)lo * kBlock + (item - s_pre[lo]);
         const unsigned td = b.dlist[pos];
         unsigned cc = wave_count_tile<ND, WIDE>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
         if (lane_id() == 0) {
