@@ -2309,22 +2309,38 @@ __device__ bool topo_tile(const Geom& g, const Bufs& b, int cur, unsigned t, con
     const TileInfo ti = tile_info(g, t);
     const int nbox = ti.BX * ti.BY * ti.BZ, BXY = ti.BX * ti.BY;
     const int ox = ti.tx * ti.TX - 1, oy = ti.ty * ti.TY - 1, oz = ti.tz * ti.TZ - ti.hz;
-    for (int k = threadIdx.x; k < nbox; k += kBlock) {
+    // the tile's record range and the box's words and labels in one round
+    // trip: every load is issued before any is used (a pixel's label is
+    // loaded beside its word and kept if the word carries none)
+    const unsigned r0 = b.tstart[cur][t], r1 = b.tstart[cur][t + 1];
+    constexpr int kPer = (kTopoBox + kBlock - 1) / kBlock;  // box cells per thread
+    unsigned long long wv[kPer];
+    unsigned short lv[kPer];
+    bool inb[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int k = (int)threadIdx.x + u * kBlock;
         const int bx = k % ti.BX, by = (k / ti.BX) % ti.BY, bz = k / BXY;
         const int x = ox + bx, y = oy + by, z = oz + bz;
-        unsigned short l = kNone;
-        unsigned long long key = kKeyInf;
-        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz) {
+        inb[u] = k < nbox && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+        wv[u] = 0ull;
+        lv[u] = kNone;
+        if (inb[u]) {
             const long long i = lin_of(g, x, y, z);
-            const unsigned long long w = word_load(words + i);
-            l = (w & 0xFFFFu) != 0xFFFFu ? (unsigned short)(w & 0xFFFFu) : b.lab[i];
-            key = w >> 16;
+            wv[u] = word_load(words + i);
+            lv[u] = b.lab[i];
         }
-        s_lab[k] = l;
-        s_key[k] = key;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int k = (int)threadIdx.x + u * kBlock;
+        if (k < nbox) {
+            const unsigned long long w = wv[u];
+            s_lab[k] = !inb[u] ? kNone : (w & 0xFFFFu) != 0xFFFFu ? (unsigned short)(w & 0xFFFFu) : lv[u];
+            s_key[k] = inb[u] ? w >> 16 : kKeyInf;
+        }
     }
     __syncthreads();
-    const unsigned r0 = b.tstart[cur][t], r1 = b.tstart[cur][t + 1];
     const uint2* rec = b.rec[cur];
     auto cell_of = [&](unsigned pos) {
         int x, y, z;
@@ -2380,18 +2396,22 @@ __device__ bool topo_tile(const Geom& g, const Bufs& b, int cur, unsigned t, con
     if (threadIdx.x == 0)
         C.n = 0;
     __syncthreads();
-    for (unsigned p = r0 + threadIdx.x; p < r1; p += kBlock)
-        if (b.tstate[p] == 1) {
+    for (unsigned p = r0 + threadIdx.x; p < r1; p += kBlock) {
+        // the record and gradient go out with the state (in bounds either way)
+        const unsigned char st = b.tstate[p];
+        const uint2 r = rec[p];
+        const float gp = grad[p];
+        if (st == 1) {
             const unsigned j = atomicAdd(&C.n, 1u);
             if (j < (unsigned)kTopoCand) {
-                const uint2 r = rec[p];
                 C.p[j] = p;
                 C.cell[j] = (unsigned short)cell_of(r.x);
                 C.rw[j] = r.y;
-                C.key[j] = cand_key(grad[p], (int)(r.y >> 16));
+                C.key[j] = cand_key(gp, (int)(r.y >> 16));
                 C.st[j] = 1;
             }
         }
+    }
     __syncthreads();
     const unsigned nc = C.n;
     int pend = 0;
