@@ -2846,8 +2846,9 @@ hipError_t launch_topo(const Geom& g, const Bufs& b, int cur, const float* grad,
 {
     hipLaunchKernelGGL(k_topo_prep, dim3(g.gp), dim3(kBlock), 0, s, g, b, cur, grad, grad_l2, flags);
     for (int r = 0; r < kTopoRounds; ++r) {
-        // later rounds have fewer tiles left: smaller grids (multiples of 8)
-        int G = g.sob_grid >> (r < 5 ? r : 5);
+        // later rounds have fewer tiles left: smaller grids (multiples of 8),
+        // but never so small that a block works through many tiles in turn
+        int G = g.sob_grid >> (r < 2 ? r : 2);
         G = G < 8 ? 8 : (G + 7) / 8 * 8;
         if (g.ndim == 3)
             hipLaunchKernelGGL(k_topo_round<3>, dim3(G), dim3(kBlock), 0, s, g, b, cur, grad, grad_l2, flags, r);
