@@ -429,6 +429,25 @@ def test_tile_shapes_agree_full_size(name):
             assert np.array_equal(x, y), f"tile {tile}: labels differ after iteration {k + 1}"
 
 
+def test_step_with_gradient_matches_step():
+    """A caller's gradient: step_with_gradient, given the context's own
+    Sobolev gradient, takes the same step as step (labels and particle sets,
+    five iterations), on a volume large enough for the flat list of dirty
+    tiles (8000 tiles, 8 per emission range)."""
+    w = W.ellipsoids3d(61, n=160, count=8, axes=(6.0, 24.0), margin=26.0)
+    print(f"[step_with_gradient shape={w.image.shape}]", flush=True)
+    a, _, _ = gpu_state(w)
+    b, _, _ = gpu_state(w)
+    for k in range(5):
+        g = S.sobolev_smooth(b, S.compute_l2_diff(b))
+        S.step_with_gradient(b, g)
+        S.step(a, S.MODE_SOBOLEV)
+        assert np.array_equal(S.get_labels(a).cpu().numpy(), S.get_labels(b).cpu().numpy()), f"labels, step {k}"
+        pa, pb = gpu_particles(a), gpu_particles(b)
+        for x, y in zip(pa, pb):
+            assert np.array_equal(x, y), f"particles, step {k}"
+
+
 def test_tile_autotune():
     """The autotuner times both cell shapes on the image and names the faster;
     a context with its choice runs like any other."""
