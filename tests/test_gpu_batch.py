@@ -117,20 +117,22 @@ def test_batch_slots_match_oracle(ora, dims, mode):
     B.close()
 
 
-def test_batch2d_64_slots_match_oracle(ora):
-    """The batched benchmark workload (64 images of 128..1024 pixels a side):
-    the smallest, a middle and the largest image checked against the oracle
-    at every one of six batched iterations, with all 64 slots live."""
+@pytest.mark.parametrize("tile", [S.TILE_DEFAULT, S.TILE_WIDE])
+def test_batch2d_64_slots_match_oracle(ora, tile):
+    """The batched benchmark workload (64 images of 128..1024 pixels a side),
+    on the default cells and on the 16x32 cells its benchmark's autotuner
+    keeps: the smallest, a middle and the largest image checked against the
+    oracle at every one of six batched iterations, with all 64 slots live."""
     ws = W.batch2d()
     ctxs = []
     for w in ws:
-        c, img, lab = S.from_workload(w)
+        c, img, lab = S.from_workload(w, tile=tile)
         S.init_labels(c, img, lab)
         ctxs.append(c)
     sizes = [w.labels.size for w in ws]
     order = np.argsort(sizes)
     shadowed = (int(order[0]), int(order[len(order) // 2]), int(order[-1]))
-    print(f"[batch2d_64 oracle: slots {shadowed}]", flush=True)
+    print(f"[batch2d_64 oracle: tile {tile} slots {shadowed}]", flush=True)
     B = S.Batch(len(ws))
     for k, c in enumerate(ctxs):
         B.set(k, c)
