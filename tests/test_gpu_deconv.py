@@ -73,12 +73,15 @@ def test_deconv_trajectory(ora, name):
     assert sh.checked == 8
 
 
-def test_deconv_full_size_first_steps(ora):
-    """The 512^2 scene with a sigma = 15 PSF: particle set, L2 and Sobolev
+@pytest.mark.parametrize("tile", [S.TILE_DEFAULT, S.TILE_WIDE])
+def test_deconv_full_size_first_steps(ora, tile):
+    """The 512^2 scene with a sigma = 15 PSF, on the default cells and on the
+    16x32 cells its benchmark's autotuner keeps: particle set, L2 and Sobolev
     gradients on every particle and the labels of the first three
     iterations, each checked from the GPU's labels."""
     w = W.make("deconv2d_512")
-    print("[case deconv2d_512]", flush=True)
+    w.tile = tile
+    print(f"[case deconv2d_512 tile {tile}]", flush=True)
     ctx, img, lab = gpu_state(w)
     sh = Shadow(ora, w, ctx).run(3)
     sh.report("deconv2d_512")
