@@ -1842,7 +1842,7 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
         // neighbour tiles k = kxi + 3 (kyi + 3 kzi), kxi < nkx, kyi < nky, kzi < nkz
         const int kown = (tx - kx0) + 3 * ((ty - ky0) + 3 * (tz - kz0));
         __syncthreads();  // the previous tile is done with LDS
-        // One round trip: the box row's slot words and L2 chunks, and (wave 0)
+        // One round trip: the box row's slot words and L2 chunks, and (the last wave)
         // the neighbour tiles' record ranges and label pairs and the tile's
         // own rows.  A row word of a tile without particles is zero, and the
         // per-pixel field holds the current L2 value at every particle, so the
@@ -1869,10 +1869,10 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
             ch[c] = ok ? *(const float4*)(dv + (size_t)(trow + (unsigned)kx) * NCORE + (e - kxo * S::TX) + S::TX * lrow)
                        : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        // wave 0: label pairs of the neighbour tiles (slot headers) and the
-        // tile's own rows for the core list
+        // the last wave (fewest box rows): label pairs of the neighbour tiles
+        // (slot headers) and the tile's own rows for the core list
         unsigned hdr = 0u, nb_beg = 0u, nb_end = 0u, own_word = 0u, own_pre = 0u;
-        if (threadIdx.x < 64) {
+        if (threadIdx.x >= kSobBlock - 64) {
             const int kxi = lane % 3, kyi = (lane / 3) % 3, kzi = lane / 9;
             if (kxi < nkx && kyi < nky && kzi < nkz) {
                 const int kx = kx0 + kxi, ky = ky0 + kyi, kz = kz0 + kzi;
@@ -1910,7 +1910,7 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
                 row[i] = make_float2(((mA >> i) & 1u) ? v : 0.f, ((mB >> i) & 1u) ? v : 0.f);
             }
         }
-        if (threadIdx.x < 64) {
+        if (threadIdx.x >= kSobBlock - 64) {
             // several label pairs around this tile: the staged generic scan
             const unsigned own_hdr = __shfl(hdr, kown);
             const bool has = nb_end > nb_beg;
