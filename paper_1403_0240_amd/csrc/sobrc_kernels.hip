@@ -699,8 +699,18 @@ __device__ __forceinline__ void xcd_chunk(unsigned na, VB vb, unsigned& a0, unsi
 {
     const unsigned G = vb.n;
     const unsigned L = (G & 7u) ? vb.id : (vb.id & 7u) * (G >> 3) + (vb.id >> 3);
-    a0 = (unsigned)((unsigned long long)L * na / G);
-    a1 = (unsigned)((unsigned long long)(L + 1) * na / G);
+    if (G < (1u << 20)) {
+        // floor(L na / G) through one double division: the product is below
+        // 2^52 (exact), the quotient below 2^32, so the correctly rounded
+        // quotient is within 2^-21 of the exact one while a fractional part
+        // is at least 1/G > 2^-20 from the next integer -- truncation is exact
+        const double dn = (double)na, dG = (double)G;
+        a0 = (unsigned)((double)L * dn / dG);
+        a1 = (unsigned)((double)(L + 1) * dn / dG);
+    } else {
+        a0 = (unsigned)((unsigned long long)L * na / G);
+        a1 = (unsigned)((unsigned long long)(L + 1) * na / G);
+    }
 }
 
 __device__ __forceinline__ bool tile_dirty(const Bufs& b, unsigned t, unsigned epoch, int all_dirty)
