@@ -1486,6 +1486,10 @@ __device__ __forceinline__ void l2diff_ps_tile_body(const Geom& g, const Bufs& b
     xcd_chunk(ds->n_active[cur], vb, a0, a1);
     const unsigned* ts = b.tstart[cur];
     const uint2* rec = b.rec[cur];
+    // box cell of this thread's first entry, and the step of kBlock entries
+    // (divisions once per block; the box walk below only adds)
+    const int bx0 = (int)threadIdx.x % BX, by0 = ((int)threadIdx.x / BX) % BY, bz0 = (int)threadIdx.x / BXY;
+    const int sx = kBlock % BX, sy = (kBlock / BX) % BY, sz = kBlock / BXY;
     for (unsigned ai = a0; ai < a1; ++ai) {
         const unsigned t = b.active[cur][ai];
         const int tx = (int)(t % (unsigned)g.ntx), ty = (int)((t / (unsigned)g.ntx) % (unsigned)g.nty);
@@ -1493,12 +1497,35 @@ __device__ __forceinline__ void l2diff_ps_tile_body(const Geom& g, const Bufs& b
         const int ox = tx * TX - R, oy = ty * TY - R, oz = tz * TZ - rz;
         const unsigned p0 = ts[t], p1 = ts[t + 1];
         __syncthreads();  // the previous tile is done with LDS
-        for (int k = threadIdx.x; k < nbox; k += kBlock) {
-            const int bx = k % BX, by = (k / BX) % BY, bz = k / BXY;
-            const int x = ox + bx, y = oy + by, z = oz + bz;
-            const bool in = x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
-            const long long j = in ? lin_of(g, x, y, z) : 0;
-            s_e[k] = make_uint2(__float_as_uint(in ? img_at(g, img, j) : 0.f), in ? (unsigned)b.lab[j] : (unsigned)kNone);
+        // the box in passes of kPsPer entries per thread: every load of a pass
+        // is issued before any entry is stored, so their latencies overlap
+        constexpr int kPsPer = 8;
+        int bx = bx0, by = by0, bz = bz0;
+        for (int k0 = 0; k0 < nbox; k0 += kBlock * kPsPer) {
+            float v[kPsPer];
+            unsigned l[kPsPer];
+#pragma unroll
+            for (int u = 0; u < kPsPer; ++u) {
+                const int k = k0 + u * kBlock + (int)threadIdx.x;
+                const int x = ox + bx, y = oy + by, z = oz + bz;
+                const bool in = k < nbox && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+                const long long j = in ? lin_of(g, x, y, z) : 0;
+                v[u] = in ? img_at(g, img, j) : 0.f;
+                l[u] = in ? (unsigned)b.lab[j] : (unsigned)kNone;
+                bx += sx;  // next entry: kBlock cells on (sx < BX, sy < BY: one carry each)
+                const int cy = bx >= BX;
+                bx -= cy ? BX : 0;
+                by += sy + cy;
+                const int cz = by >= BY;
+                by -= cz ? BY : 0;
+                bz += sz + cz;
+            }
+#pragma unroll
+            for (int u = 0; u < kPsPer; ++u) {
+                const int k = k0 + u * kBlock + (int)threadIdx.x;
+                if (k < nbox)
+                    s_e[k] = make_uint2(__float_as_uint(v[u]), l[u]);
+            }
         }
         __syncthreads();
         for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
