@@ -819,6 +819,7 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     __shared__ unsigned s_pre[kMaxGrid + 1];
     __shared__ unsigned s_red[kBlock / 64];
     static_assert(kMaxGrid == 8 * kBlock, "eight list lengths per thread");
+    static_assert(kMaxGrid <= 64 * 64, "two probes of 64 positions cover the prefix");
     const int ge = g.ge;
     const int i0 = (int)threadIdx.x * 8;
     const uint4* dc = (const uint4*)b.dcnt;  // kMaxGrid entries; only those < ge are read
@@ -847,18 +848,21 @@ __device__ __forceinline__ void count_list_body(const Geom& g, const Bufs& b, in
     __syncthreads();
     if (vb.id == 0 && threadIdx.x == 0)
         b.ds->ndirty = tot;
-    const int wv = threadIdx.x >> 6;
+    const int wv = threadIdx.x >> 6, lane = lane_id();
     unsigned a0, a1;
     xcd_chunk(tot, vb, a0, a1);
     for (unsigned item = a0 + wv; item < a1; item += kBlock / 64) {
-        int lo = 0, hi = ge;  // list block holding item: the largest lo with s_pre[lo] <= item
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_pre[mid] <= item)
-                lo = mid;
-            else
-                hi = mid;
-        }
+        // list block holding item: the largest lo with s_pre[lo] <= item.  The
+        // prefix is non-decreasing with s_pre[0] = 0, so the wave finds it in
+        // two probes of 64 positions (chunks of S, then within the chunk)
+        // instead of a chain of dependent LDS reads
+        const int S = (ge + 63) >> 6;
+        const int p1 = lane * S;
+        const bool c1 = p1 < ge && s_pre[p1] <= item;
+        const int lo1 = (__popcll(__ballot(c1)) - 1) * S;
+        const int p2 = lo1 + lane;
+        const bool c2 = lane < S && p2 < ge && s_pre[p2] <= item;
+        const int lo = lo1 + __popcll(__ballot(c2)) - 1;
         const unsigned pos = (unsigned)lo * kBlock + (item - s_pre[lo]);
         const unsigned td = b.dlist[pos];
         unsigned cc = wave_count_tile<ND, WIDE>(g, b.lab, b.labt, td, W[wv], b.tslot + (size_t)td * kSlotWords);
