@@ -260,8 +260,9 @@ int32_t get_gradient_mode(sobrc_ctx* ctx, int32_t* h_switch_iter, void* stream);
  * events on `stream`, in two rounds with the shapes alternating.  h_ms[3]
  * receives the milliseconds per iteration (the faster round) of
  * SOBRC_TILE_DEFAULT, SOBRC_TILE_WIDE and SOBRC_TILE_TALL (-1 for a shape not
- * admitted); *h_tile is the fastest other shape if that is at least 1 %
- * faster than the default, else the default.  Results do not depend on the shape, so a caller then creates its
+ * admitted); *h_tile is the fastest other shape if that is at least 1.5 %
+ * faster than the default (the trials' timing noise reaches about 1 %), else
+ * the default.  Results do not depend on the shape, so a caller then creates its
  * context with that tile.  d_workspace: device memory of at
  * least tile_autotune_workspace_size bytes, 256-byte aligned, owned by the
  * caller; its contents are scratch.  Synchronous.  EINVAL for NULL arguments

@@ -1882,7 +1882,8 @@ __device__ __forceinline__ void brick_range(const Geom& g, const Bufs& b, const 
         const int kz0 = bz0 / S::TZ, nkz = (bz1 - 1) / S::TZ - kz0 + 1;
         // neighbour tiles k = kxi + 3 (kyi + 3 kzi), kxi < nkx, kyi < nky, kzi < nkz
         const int kown = (tx - kx0) + 3 * ((ty - ky0) + 3 * (tz - kz0));
-        __syncthreads();  // the previous tile is done with LDS
+        if (ai != a0)
+            __syncthreads();  // the previous tile is done with LDS
         // One round trip: the box row's slot words and L2 chunks, and (the last wave)
         // the neighbour tiles' record ranges and label pairs and the tile's
         // own rows.  A row word of a tile without particles is zero, and the
@@ -3072,6 +3073,8 @@ __global__ __launch_bounds__(kSobBlock) void kb_sobolev_brick(const ImgDesc* __r
         const int i = slot_of(tpre, nslot, k);  // slot whose run holds tile k (never an empty one)
         const unsigned e = min(a1, tpre[i + 1]);
         const ImgDesc& D = d[i];
+        if (k != a0)
+            __syncthreads();  // the previous slot's tiles are done with LDS
         brick_range<ND, H, FULL, WIDE>(D.g, D.b, sw, (int)par[i], D.b.dE, D.b.gH1, gated, k - tpre[i], e - tpre[i]);
         k = e;
     }

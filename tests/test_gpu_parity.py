@@ -458,7 +458,7 @@ def test_tile_autotune():
         assert tile in (S.TILE_DEFAULT, S.TILE_WIDE)
         assert ms[0] > 0 and ms[1] > 0 and (ms[2] > 0) == (w.ndim == 2) and (ms[2] == -1.0) == (w.ndim == 3)
         alt = 1 if w.ndim == 3 or ms[1] <= ms[2] else 2
-        assert tile == (alt if ms[alt] < 0.99 * ms[0] else S.TILE_DEFAULT)
+        assert tile == (alt if ms[alt] < 0.985 * ms[0] else S.TILE_DEFAULT)
         w.tile = tile
         ctx, img, lab = gpu_state(w)
         assert S.run(ctx, 3) == 3
